@@ -1,0 +1,141 @@
+/*
+ * qwexp -- exp(-i t H) psi on the n-qubit hypercube for MI355X (gfx950).
+ *
+ * H = H_P + gamma * H_G with H_P diagonal (Ising energies E(z)) and
+ * H_G = sum_j X_j (section I of Hopkins & Kendon, "Numerical methods for the
+ * simulation of quantum walks and quantum annealing").  The action is evaluated
+ * as a Chebyshev series of exp(-i a x) (Bessel coefficients, Eq. cheb, or the
+ * Caratheodory-Fejer correction of section II.C) by the matrix Clenshaw
+ * recurrence (Alg. 2, Eq. recursion) with a matrix-free H_G (section II.D).
+ *
+ * Conventions shared by every entry point
+ *   - Qubit j is bit j of the basis index z; s_j(z) = 1 - 2*bit_j(z).
+ *   - Complex vectors are interleaved (re, im): complex64 = 2 x float,
+ *     complex128 = 2 x double, i.e. torch.complex64 / torch.complex128 storage.
+ *   - "device" pointers are HIP device allocations on the current device;
+ *     "host" pointers are ordinary host memory.  The caller owns all memory.
+ *     The library allocates nothing on the device: all scratch comes from the
+ *     caller's workspace (size from qw_workspace_bytes / the batched and
+ *     gradient size queries).
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *     enqueue their kernels on it.  Entry points that need the spectral bound
+ *     read 16 bytes back and synchronise the stream once.
+ *   - Errors: every call returns a qw_status; nothing is thrown across the ABI.
+ *     qw_last_error() returns a thread-local message for the last failure.
+ *   - Calls on distinct workspaces may run concurrently from different threads.
+ */
+#ifndef QWEXP_H
+#define QWEXP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QW_OK = 0,
+    QW_EINVAL = -1,    /* bad size, tolerance, pointer or non-finite scalar      */
+    QW_ENOMEM = -2,    /* workspace smaller than required                        */
+    QW_EHIP = -3,      /* a HIP runtime call failed                              */
+    QW_EDIVERGE = -4,  /* the recurrence grew past its bound (radius too small)  */
+    QW_ENOCONV = -5    /* coefficient setup did not converge                     */
+} qw_status;
+
+typedef enum { QW_CHEB = 0, QW_CF = 1 } qw_method;
+
+/* Filled on the host before an action call returns (may be NULL). */
+typedef struct {
+    int n;              /* qubits                                                 */
+    int K;              /* polynomial degree; K+1 coefficients                    */
+    int passes;         /* global passes per Clenshaw term                        */
+    int method;         /* qw_method actually used                                */
+    double shift_c;     /* spectral shift c = (max E + min E)/2                   */
+    double radius_r;    /* bound r on the spectral radius of H - cI               */
+    double a;           /* t * r, the argument of the Bessel coefficients         */
+    double trunc_bound; /* truncation bound (Chebyshev tail sum or CF estimate)   */
+    double eval_bound;  /* a-priori evaluation-error bound, section II.B.3        */
+} qw_info;
+
+/* Chebyshev coefficients of exp(-i a x) on [-1, 1] (section II.B.1, Eq. cheb,
+ * with a -> -a; section II.C for QW_CF).  Host only.
+ *   alpha : host, kmax+1 doubles; receives alpha_0..alpha_K with
+ *           c_m = (-i)^m alpha_m (Chebyshev: alpha_0 = J_0(a), alpha_m = 2 J_m(a)).
+ *   K_out : host int, the degree K (smallest whose truncation bound <= tol).
+ *   err   : host double (may be NULL), the truncation bound of Eq. TruncError
+ *           (Chebyshev) or |lambda_cos| + |lambda_sin| (CF).
+ * Returns QW_EINVAL for tol <= 0 or non-finite a, QW_ENOMEM if K > kmax. */
+qw_status qw_cheb_coeffs(double a, double tol, qw_method method, int kmax,
+                         double *alpha, int *K_out, double *err);
+
+/* Bessel values J_0(a) .. J_mmax(a) by Miller's backward recurrence (section
+ * II.B.1) in double precision, normalised by J_0 + 2 sum J_2m = 1.  Host only;
+ * J: host, mmax+1 doubles. */
+qw_status qw_bessel_j(double a, int mmax, double *J);
+
+/* Workspace bytes for one action call on n qubits at precision 64 (complex64
+ * state, float diagonal) or 128 (complex128, double diagonal).  on_the_fly != 0
+ * sizes the variant that never stores the diagonal (diag == NULL, n >= 31 or
+ * forced by the flag of the action call). */
+size_t qw_workspace_bytes(int n, int precision, int on_the_fly);
+
+/* Shift c and bound r of H - cI (section II.A): c = (max E + min E)/2,
+ * r = (max E - min E)/2 + n |gamma| (the induced 1-norm).
+ *   diag : device, N = 2^n energies (float for _f32, double for _f64), or NULL
+ *          to compute E(z) = sum_{j<k} J_jk s_j s_k + sum_j h_j s_j on device
+ *          from h (host, n doubles) and J (host, packed row-major upper
+ *          triangle, n(n-1)/2 doubles).
+ *   workspace : device, >= qw_workspace_bytes(n, 64|128, 0) bytes.
+ * Synchronises the stream (16-byte read-back). */
+qw_status qw_spectral_bound_f32(int n, const float *diag, const double *h, const double *J,
+                                double gamma, double *c, double *r,
+                                void *workspace, size_t ws_bytes, void *stream);
+qw_status qw_spectral_bound_f64(int n, const double *diag, const double *h, const double *J,
+                                double gamma, double *c, double *r,
+                                void *workspace, size_t ws_bytes, void *stream);
+
+/* psi_out = exp(-i t (diag(E) + gamma sum_j X_j)) psi_in  (section I, Eq.
+ * SchroedSol), global phase exp(-i t c) of the spectral shift restored.
+ *   n       : 1..32.
+ *   diag    : device, N energies (float for _c64, double for _c128), or NULL to
+ *             generate them from h, J (host arrays as in qw_spectral_bound_*).
+ *             With diag == NULL and n >= 31 the diagonal is recomputed inside
+ *             every Clenshaw term from per-tile tables and never stored.
+ *   psi_in  : device, N complex values; psi_out: device, N complex values; they
+ *             may be the same buffer.
+ *   tol     : truncation tolerance (absolute, for a unit-norm psi).
+ *   method  : QW_CHEB or QW_CF.
+ *   workspace : device, >= qw_workspace_bytes(n, 64|128, on_the_fly) bytes,
+ *             256-byte aligned.
+ *   info    : host, optional.
+ * Complex64 rounds gamma/r towards zero to float and redefines r = gamma/that,
+ * so the hypercube term carries no rounding; the normalised diagonal is
+ * formed in double and rounded once to float.  Enqueues ~K*passes kernels on
+ * stream after one synchronising 16-byte read-back. */
+qw_status qw_expm_action_c64(int n, const float *diag, const double *h, const double *J,
+                             double gamma, double t, const void *psi_in, void *psi_out,
+                             double tol, qw_method method,
+                             void *workspace, size_t ws_bytes, void *stream, qw_info *info);
+qw_status qw_expm_action_c128(int n, const double *diag, const double *h, const double *J,
+                              double gamma, double t, const void *psi_in, void *psi_out,
+                              double tol, qw_method method,
+                              void *workspace, size_t ws_bytes, void *stream, qw_info *info);
+
+const char *qw_last_error(void);
+
+/* Host-only self check of the tile index maps used by the Clenshaw passes for
+ * n qubits at precision 64 or 128: every (tile, element) pair must address each
+ * amplitude exactly once and every flipped partner must stay inside its tile.
+ * Returns the number of passes per term, or a negative code on a violation.
+ * Launches nothing. */
+int qw_debug_check_plan(int n, int precision);
+
+/* Library version string. */
+const char *qw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QWEXP_H */

@@ -1,0 +1,222 @@
+"""qwexp: exp(-i t H) psi on the n-qubit hypercube, MI355X (gfx950) HIP kernels.
+
+Thin ctypes binding over ``libqwexp.so`` (C-ABI declared in include/qwexp.h).
+Every step of the computation runs in the library; this module only marshals
+arguments: torch tensors supply device memory and the current HIP stream.
+
+H = diag(E) + gamma * sum_j X_j with E(z) the Ising energies (given as a device
+vector, or generated on the device from the SK couplings h, J).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqwexp.so")
+
+QW_OK, QW_EINVAL, QW_ENOMEM, QW_EHIP, QW_EDIVERGE, QW_ENOCONV = 0, -1, -2, -3, -4, -5
+QW_CHEB, QW_CF = 0, 1
+_METHODS = {"cheb": QW_CHEB, "chebyshev": QW_CHEB, "cf": QW_CF}
+_STATUS = {0: "QW_OK", -1: "QW_EINVAL", -2: "QW_ENOMEM", -3: "QW_EHIP", -4: "QW_EDIVERGE", -5: "QW_ENOCONV"}
+
+
+class QwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class QwInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("K", ctypes.c_int), ("passes", ctypes.c_int), ("method", ctypes.c_int),
+                ("shift_c", ctypes.c_double), ("radius_r", ctypes.c_double), ("a", ctypes.c_double),
+                ("trunc_bound", ctypes.c_double), ("eval_bound", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_sz = ctypes.c_size_t
+
+
+def _declare(lib):
+    lib.qw_last_error.restype = ctypes.c_char_p
+    lib.qw_version.restype = ctypes.c_char_p
+    lib.qw_workspace_bytes.restype = _sz
+    lib.qw_workspace_bytes.argtypes = [_i, _i, _i]
+    lib.qw_bessel_j.argtypes = [_d, _i, _dp]
+    lib.qw_cheb_coeffs.argtypes = [_d, _d, _i, _i, _dp, ctypes.POINTER(_i), _dp]
+    for name in ("qw_spectral_bound_f32", "qw_spectral_bound_f64"):
+        f = getattr(lib, name)
+        f.argtypes = [_i, _vp, _dp, _dp, _d, _dp, _dp, _vp, _sz, _vp]
+    for name in ("qw_expm_action_c64", "qw_expm_action_c128"):
+        f = getattr(lib, name)
+        f.argtypes = [_i, _vp, _dp, _dp, _d, _d, _vp, _vp, _d, _i, _vp, _sz, _vp, ctypes.POINTER(QwInfo)]
+    lib.qw_debug_check_plan.argtypes = [_i, _i]
+    lib.qw_debug_check_plan.restype = _i
+    return lib
+
+
+def lib():
+    """Load libqwexp.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2608_12058_amd.build` "
+                              "(there is no CPU fallback)")
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def _check(status: int):
+    if status != QW_OK:
+        raise QwError(status, lib().qw_last_error().decode())
+
+
+def version() -> str:
+    return lib().qw_version().decode()
+
+
+# ------------------------------------------------------------------ host calls
+
+def bessel_j(a: float, mmax: int) -> np.ndarray:
+    out = np.empty(mmax + 1, dtype=np.float64)
+    _check(lib().qw_bessel_j(float(a), int(mmax), out.ctypes.data_as(_dp)))
+    return out
+
+
+def cheb_coeffs(a: float, tol: float, method: str = "cheb", kmax: int = 1 << 20) -> tuple[np.ndarray, float]:
+    """alpha_0..alpha_K with c_m = (-i)^m alpha_m, and the truncation bound."""
+    buf = np.empty(kmax + 1, dtype=np.float64)
+    K = _i(0)
+    err = _d(0.0)
+    _check(lib().qw_cheb_coeffs(float(a), float(tol), _METHODS[method], int(kmax), buf.ctypes.data_as(_dp),
+                                ctypes.byref(K), ctypes.byref(err)))
+    return buf[:K.value + 1].copy(), err.value
+
+
+def workspace_bytes(n: int, precision: int = 64, on_the_fly: bool = False) -> int:
+    return int(lib().qw_workspace_bytes(int(n), int(precision), 1 if on_the_fly else 0))
+
+
+# ------------------------------------------------------------------ device calls
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _host_f64(x, count):
+    if x is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if arr.shape != (count,):
+        raise ValueError(f"expected {count} values, got shape {arr.shape}")
+    return arr, arr.ctypes.data_as(_dp)
+
+
+@dataclass
+class Workspace:
+    """Device scratch for one action call, owned by the caller (torch uint8)."""
+    tensor: object
+    nbytes: int
+
+    @staticmethod
+    def for_problem(n: int, precision: int = 64, on_the_fly: bool = False, device="cuda"):
+        torch = _torch()
+        nb = workspace_bytes(n, precision, on_the_fly)
+        t = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+        return Workspace(t, nb)
+
+    def ptr(self) -> int:
+        p = self.tensor.data_ptr()
+        return (p + 255) & ~255
+
+
+def _prec_of(psi) -> int:
+    torch = _torch()
+    if psi.dtype == torch.complex64:
+        return 64
+    if psi.dtype == torch.complex128:
+        return 128
+    raise TypeError("psi must be complex64 or complex128")
+
+
+def spectral_bound(n: int, gamma: float, diag=None, h=None, J=None, precision: int = 64,
+                   workspace: Workspace | None = None, stream=None) -> tuple[float, float]:
+    """(c, r): shift and induced 1-norm bound of H - cI."""
+    torch = _torch()
+    if workspace is None:
+        workspace = Workspace.for_problem(n, precision, diag is None and n >= 31)
+    _, hp = _host_f64(h, n) if diag is None else (None, None)
+    _, Jp = _host_f64(J, n * (n - 1) // 2) if diag is None else (None, None)
+    if diag is not None:
+        want = torch.float32 if precision == 64 else torch.float64
+        if diag.dtype != want or not diag.is_contiguous() or diag.numel() != (1 << n):
+            raise ValueError("diag must be a contiguous vector of 2^n energies in the state's real precision")
+    c, r = _d(0.0), _d(0.0)
+    fn = lib().qw_spectral_bound_f32 if precision == 64 else lib().qw_spectral_bound_f64
+    _check(fn(int(n), _vp(diag.data_ptr()) if diag is not None else None, hp, Jp, float(gamma),
+              ctypes.byref(c), ctypes.byref(r), _vp(workspace.ptr()), workspace.nbytes, _stream_ptr(stream)))
+    return c.value, r.value
+
+
+def expm_action(psi, gamma: float, t: float, *, diag=None, h=None, J=None, tol: float = 2.0 ** -23,
+                method: str = "cheb", out=None, workspace: Workspace | None = None, stream=None):
+    """psi(t) = exp(-i t (diag(E) + gamma sum_j X_j)) psi on the GPU.
+
+    psi: contiguous complex64 or complex128 CUDA tensor of length 2^n.
+    diag: CUDA tensor of 2^n energies (float32 for complex64, float64 for
+    complex128) or None with h (n values) and J (n(n-1)/2 values, packed upper
+    triangle) given as host arrays.  Returns (psi_out, info dict)."""
+    torch = _torch()
+    if not (psi.is_cuda and psi.is_contiguous() and psi.dim() == 1):
+        raise ValueError("psi must be a contiguous 1-D CUDA tensor")
+    N = psi.numel()
+    n = N.bit_length() - 1
+    if N != (1 << n):
+        raise ValueError("len(psi) must be a power of two")
+    prec = _prec_of(psi)
+    if out is None:
+        out = torch.empty_like(psi)
+    elif out.dtype != psi.dtype or out.numel() != N or not out.is_contiguous():
+        raise ValueError("out must match psi")
+    if diag is not None:
+        want = torch.float32 if prec == 64 else torch.float64
+        if diag.dtype != want or not diag.is_contiguous() or diag.numel() != N or not diag.is_cuda:
+            raise ValueError("diag must be a contiguous CUDA vector of 2^n energies in the state's real precision")
+        hp = Jp = None
+    else:
+        if h is None or J is None:
+            raise ValueError("give diag, or h and J")
+        _h, hp = _host_f64(h, n)
+        _J, Jp = _host_f64(J, n * (n - 1) // 2)
+    otf = diag is None and n >= 31
+    if workspace is None:
+        workspace = Workspace.for_problem(n, prec, otf, device=psi.device)
+    info = QwInfo()
+    fn = lib().qw_expm_action_c64 if prec == 64 else lib().qw_expm_action_c128
+    _check(fn(int(n), _vp(diag.data_ptr()) if diag is not None else None, hp, Jp, float(gamma), float(t),
+              _vp(psi.data_ptr()), _vp(out.data_ptr()), float(tol), _METHODS[method],
+              _vp(workspace.ptr()), workspace.nbytes, _stream_ptr(stream), ctypes.byref(info)))
+    return out, info.as_dict()
+
+
+def debug_check_plan(n: int, precision: int) -> int:
+    """Host-only check of the pass index maps (number of passes, or < 0)."""
+    return int(lib().qw_debug_check_plan(int(n), int(precision)))

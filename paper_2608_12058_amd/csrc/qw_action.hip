@@ -1,0 +1,925 @@
+// exp(-i t H) psi for H = diag(E) + gamma sum_j X_j: kernels and C-ABI.
+//
+// Method (Hopkins & Kendon): shift and bound the spectrum (section II.A),
+// expand exp(-i a x) in Chebyshev polynomials (Eq. cheb, or the CF correction of
+// section II.C), and evaluate with the matrix Clenshaw recurrence
+// (Alg. 2 / Eq. recursion) written in place into the b_{k+2} buffer
+// (section II.D), with the hypercube sum applied matrix-free.
+//
+// Device layout: psi, b1, b2 are interleaved complex vectors of N = 2^n
+// amplitudes (bit j of the index = qubit j); the normalised diagonal
+// d = (E - c)/r is a real vector of N (or recomputed per tile for n >= 31).
+//
+// Per Clenshaw term the state is streamed in P passes (P = 1 for n <= 13 in
+// complex64): the first pass loads a contiguous tile of 2^13 amplitudes of
+// b_{k+1} into LDS, sums the flips of its low 13 bits, and fuses the diagonal,
+// the coefficient axpy and the three-term update; each further pass loads a
+// tile spanning a group of high bits (plus contiguous "passenger" bits for
+// coalescing) and adds that group's flips.  Small instances (n <= 13) run the
+// whole recurrence inside one workgroup with the vector resident in LDS.
+#include "qw_device.h"
+#include "qw_internal.h"
+#include "qwexp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace qw {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+// ---------------------------------------------------------------------------
+// Compile-time configuration
+// ---------------------------------------------------------------------------
+template <typename R> struct Cfg;
+template <> struct Cfg<float> {
+    static constexpr int TB = 13;     // tile bits of a pass (2^13 x 8 B = 64 KB LDS)
+    static constexpr int NT = 512;    // threads per pass workgroup
+    static constexpr int LMIN = 4;    // passenger bits: rows of >= 128 B
+};
+template <> struct Cfg<double> {
+    static constexpr int TB = 12;     // 2^12 x 16 B = 64 KB LDS
+    static constexpr int NT = 512;
+    static constexpr int LMIN = 3;
+};
+static constexpr int ONCHIP_NT = 1024;
+static constexpr int MAXPART = 4096;          // reduction partials
+static constexpr int KMAX_ONCHIP = 1 << 17;   // coefficient slots for on-chip runs
+static constexpr int LB_TAB = 13;             // low bits of the energy tables
+
+// ---------------------------------------------------------------------------
+// Kernels: energies, spectral bound, normalisation
+// ---------------------------------------------------------------------------
+
+// Q[lo] = sum_{j<k<LB} J_jk s_j(lo) s_k(lo).
+__global__ void k_qtable(EnergyTables T, double *Q)
+{
+    const uint32_t lo = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lo >= (1u << T.LB)) return;
+    double acc = 0.0;
+    for (int j = 0; j < T.LB; ++j) {
+        const double sj = ((lo >> j) & 1) ? -1.0 : 1.0;
+        double fj = 0.0;
+        for (int k = j + 1; k < T.LB; ++k) {
+            const double Jk = T.J[pair_off(T.n, j, k)];
+            fj += ((lo >> k) & 1) ? -Jk : Jk;
+        }
+        acc += sj * fj;
+    }
+    Q[lo] = acc;
+}
+
+__device__ inline void block_minmax(double lo, double hi, double *part)
+{
+    __shared__ double smin[256], smax[256];
+    smin[threadIdx.x] = lo;
+    smax[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = smin[0];
+        part[2 * blockIdx.x + 1] = smax[0];
+    }
+}
+
+// Min / max of E over all z generated from the tables (grid-stride over tiles
+// of 2^LB consecutive indices).  256 threads.
+__global__ void __launch_bounds__(256) k_minmax_energy(EnergyTables T, double *part)
+{
+    __shared__ double f[LB_TAB];
+    __shared__ double Cc;
+    const uint64_t ntiles = uint64_t(1) << (T.n - T.LB);
+    const uint32_t TE = 1u << T.LB;
+    double mn = INFINITY, mx = -INFINITY;
+    for (uint64_t hi = blockIdx.x; hi < ntiles; hi += gridDim.x) {
+        __syncthreads();
+        tile_fields(T, hi, f, &Cc);
+        __syncthreads();
+        for (uint32_t lo = threadIdx.x; lo < TE; lo += blockDim.x) {
+            double e = Cc + T.Q[lo];
+            for (int j = 0; j < T.LB; ++j) e += ((lo >> j) & 1) ? -f[j] : f[j];
+            mn = fmin(mn, e);
+            mx = fmax(mx, e);
+        }
+    }
+    block_minmax(mn, mx, part);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_minmax_diag(const R *d, uint64_t N, double *part)
+{
+    double mn = INFINITY, mx = -INFINITY;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const double v = (double)d[i];
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
+    }
+    block_minmax(mn, mx, part);
+}
+
+__global__ void __launch_bounds__(256) k_minmax_final(const double *part, int np, double *out)
+{
+    double mn = INFINITY, mx = -INFINITY;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        mn = fmin(mn, part[2 * i]);
+        mx = fmax(mx, part[2 * i + 1]);
+    }
+    __shared__ double smin[256], smax[256];
+    smin[threadIdx.x] = mn;
+    smax[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = smin[0];
+        out[1] = smax[0];
+    }
+}
+
+// d[z] = (E(z) - c) / r formed in double, rounded once to R.
+template <typename R>
+__global__ void __launch_bounds__(256) k_normalize_energy(EnergyTables T, double c, double inv_r, R *d)
+{
+    __shared__ double f[LB_TAB];
+    __shared__ double Cc;
+    const uint64_t ntiles = uint64_t(1) << (T.n - T.LB);
+    const uint32_t TE = 1u << T.LB;
+    for (uint64_t hi = blockIdx.x; hi < ntiles; hi += gridDim.x) {
+        __syncthreads();
+        tile_fields(T, hi, f, &Cc);
+        __syncthreads();
+        for (uint32_t lo = threadIdx.x; lo < TE; lo += blockDim.x) {
+            double e = Cc + T.Q[lo];
+            for (int j = 0; j < T.LB; ++j) e += ((lo >> j) & 1) ? -f[j] : f[j];
+            d[(hi << T.LB) | lo] = (R)((e - c) * inv_r);
+        }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_normalize_diag(const R *E, uint64_t N, double c, double inv_r, R *d)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        d[i] = (R)(((double)E[i] - c) * inv_r);
+}
+
+// Q~ = Q / r rounded to float, for the per-term diagonal of the on-the-fly form.
+__global__ void k_qtilde(const double *Q, int LB, double inv_r, float *Qt)
+{
+    const uint32_t lo = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lo < (1u << LB)) Qt[lo] = (float)(Q[lo] * inv_r);
+}
+
+// ---------------------------------------------------------------------------
+// Kernels: Clenshaw recurrence
+// ---------------------------------------------------------------------------
+
+// b1 = c_K psi, b2 = 0   (Eq. recursion: b_K = c_K v, b_{K+1} = 0)
+template <typename R>
+__global__ void __launch_bounds__(256) k_init(const CVec<R> *psi, CVec<R> *b1, CVec<R> *b2,
+                                              R cr, R ci, uint64_t nvec)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nvec;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const CVec<R> p = psi[i];
+        CVec<R> o, z;
+#pragma unroll
+        for (int v = 0; v < CVec<R>::N; ++v) {
+            o.v[v].x = cr * p.v[v].x - ci * p.v[v].y;
+            o.v[v].y = cr * p.v[v].y + ci * p.v[v].x;
+            z.v[v].x = R(0);
+            z.v[v].y = R(0);
+        }
+        b1[i] = o;
+        b2[i] = z;
+    }
+}
+
+// out = (cr + i ci) psi   (K = 0 or a zero spectral bound)
+template <typename R>
+__global__ void __launch_bounds__(256) k_scale(const CVec<R> *psi, CVec<R> *out, R cr, R ci, uint64_t nvec)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nvec;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const CVec<R> p = psi[i];
+        CVec<R> o;
+#pragma unroll
+        for (int v = 0; v < CVec<R>::N; ++v) {
+            o.v[v].x = cr * p.v[v].x - ci * p.v[v].y;
+            o.v[v].y = cr * p.v[v].y + ci * p.v[v].x;
+        }
+        out[i] = o;
+    }
+}
+
+template <typename R> struct PassArgs {
+    using C = typename Cplx<R>::T;
+    const C *b1;   // b_{k+1}: its flips over the tile's group are summed
+    const C *acc;  // START: b_{k+2};  ADD: the partial b_k
+    C *dst;        // output, may alias acc
+    const C *psi;  // START: v
+    const R *d;    // START: normalised diagonal (unless on the fly)
+    const float *Qt;   // on the fly: Q / r table over the low 13 bits
+    const double *hJ;  // on the fly: h then J (device)
+    double otf_c, otf_inv_r;
+    R g;           // gamma / r
+    R scale;       // 2 inside the recurrence, 1 for the final step
+    R cr, ci;      // START: c_k
+    R pr, pi;      // multiplier of the result (the global phase on the last pass)
+    int n, L, g0, h;
+};
+
+// One pass of one Clenshaw term over one tile (see tile_base/tile_index).
+//  START: dst = scale * (d .* b1 + g * F_group b1) - acc + c_k psi
+//  ADD:   dst = acc + scale * g * F_group b1
+// then dst *= (pr + i pi).  F_group sums the flips of the tile's h group bits.
+template <typename R, int TB, int NT, bool START, bool OTF>
+__global__ void __launch_bounds__(NT) k_pass(PassArgs<R> a)
+{
+    using C = typename Cplx<R>::T;
+    using V = CVec<R>;
+    constexpr int VE = V::N;
+    constexpr int PER = (1 << TB) / (NT * VE);
+    static_assert(PER >= 1, "tile smaller than one vector per thread");
+    __shared__ C lds[1 << TB];
+    __shared__ float fld[OTF ? LB_TAB : 1];
+    __shared__ float fbase;
+
+    const uint32_t TE = 1u << (a.L + a.h);
+    const uint64_t base = tile_base(blockIdx.x, a.L, a.g0, a.h);
+
+    if constexpr (OTF) {
+        // Per-tile fields of the diagonal: the tile is the contiguous block of
+        // the low 13 bits, so its high bits are fixed (blockIdx.x).
+        __shared__ double f64[LB_TAB];
+        __shared__ double c64;
+        EnergyTables T{a.hJ, a.hJ + a.n, nullptr, a.n, LB_TAB};
+        tile_fields(T, (uint64_t)blockIdx.x, f64, &c64);
+        __syncthreads();
+        if (threadIdx.x < LB_TAB) fld[threadIdx.x] = (float)(f64[threadIdx.x] * a.otf_inv_r);
+        if (threadIdx.x == 0) fbase = (float)((c64 - a.otf_c) * a.otf_inv_r);
+    }
+
+    V own[PER], accv[PER];
+    V psiv[START ? PER : 1];
+    R dv[START ? PER : 1][VE];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
+        if (e < TE) {
+            const uint64_t idx = tile_index(base, e, a.L, a.g0);
+            own[q] = *reinterpret_cast<const V *>(a.b1 + idx);
+            accv[q] = *reinterpret_cast<const V *>(a.acc + idx);
+            if constexpr (START) {
+                psiv[q] = *reinterpret_cast<const V *>(a.psi + idx);
+                if constexpr (!OTF) {
+#pragma unroll
+                    for (int v = 0; v < VE; ++v) dv[q][v] = a.d[idx + v];
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < VE; ++v) lds[e + v] = own[q].v[v];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
+        if (e < TE) {
+            const uint64_t idx = tile_index(base, e, a.L, a.g0);
+            V out;
+#pragma unroll
+            for (int v = 0; v < VE; ++v) {
+                const uint32_t ee = e + v;
+                R sr = R(0), si = R(0);
+                for (int j = 0; j < a.h; ++j) {
+                    const C nb = lds[ee ^ (1u << (a.L + j))];
+                    sr += nb.x;
+                    si += nb.y;
+                }
+                C o;
+                if constexpr (START) {
+                    R dd;
+                    if constexpr (OTF) {
+                        float s = fbase + a.Qt[ee];
+#pragma unroll
+                        for (int j = 0; j < LB_TAB; ++j) s += ((ee >> j) & 1) ? -fld[j] : fld[j];
+                        dd = (R)s;
+                    } else {
+                        dd = dv[q][v];
+                    }
+                    const C b = own[q].v[v], ac = accv[q].v[v], ps = psiv[q].v[v];
+                    const R hr = dd * b.x + a.g * sr;
+                    const R hi = dd * b.y + a.g * si;
+                    o.x = (a.scale * hr - ac.x) + (a.cr * ps.x - a.ci * ps.y);
+                    o.y = (a.scale * hi - ac.y) + (a.cr * ps.y + a.ci * ps.x);
+                } else {
+                    const C ac = accv[q].v[v];
+                    const R sg = a.scale * a.g;
+                    o.x = ac.x + sg * sr;
+                    o.y = ac.y + sg * si;
+                }
+                out.v[v].x = a.pr * o.x - a.pi * o.y;
+                out.v[v].y = a.pr * o.y + a.pi * o.x;
+            }
+            *reinterpret_cast<V *>(a.dst + idx) = out;
+        }
+    }
+}
+
+// Whole recurrence of one small instance (n <= TB) inside one workgroup.
+template <typename R> struct OnchipItem {
+    using C = typename Cplx<R>::T;
+    const C *psi;
+    C *out;
+    const R *d;
+    const C *coef;  // c_0..c_K
+    R g;
+    R pr, pi;       // global phase
+    int n, K;
+};
+
+template <typename R, int TB, int NT>
+__global__ void __launch_bounds__(NT) k_onchip(const OnchipItem<R> *items, const int *order, int count)
+{
+    using C = typename Cplx<R>::T;
+    constexpr int PER = (1 << TB) / NT;
+    static_assert(PER >= 1, "");
+    __shared__ C lds[1 << TB];
+    for (int it = blockIdx.x; it < count; it += gridDim.x) {
+        const OnchipItem<R> I = items[order ? order[it] : it];
+        const uint32_t N = 1u << I.n;
+        C ps[PER], b1[PER], b2[PER];
+        R dd[PER];
+        const C cK = I.coef[I.K];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t e = q * NT + threadIdx.x;
+            if (e < N) {
+                ps[q] = I.psi[e];
+                dd[q] = I.d[e];
+                b1[q].x = cK.x * ps[q].x - cK.y * ps[q].y;
+                b1[q].y = cK.x * ps[q].y + cK.y * ps[q].x;
+                b2[q].x = R(0);
+                b2[q].y = R(0);
+                lds[e] = b1[q];
+            }
+        }
+        __syncthreads();
+        for (int k = I.K - 1; k >= 1; --k) {
+            const C ck = I.coef[k];
+            C nb[PER];
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const uint32_t e = q * NT + threadIdx.x;
+                if (e < N) {
+                    R sr = R(0), si = R(0);
+                    for (int j = 0; j < I.n; ++j) {
+                        const C x = lds[e ^ (1u << j)];
+                        sr += x.x;
+                        si += x.y;
+                    }
+                    const R hr = dd[q] * b1[q].x + I.g * sr;
+                    const R hi = dd[q] * b1[q].y + I.g * si;
+                    nb[q].x = (R(2) * hr - b2[q].x) + (ck.x * ps[q].x - ck.y * ps[q].y);
+                    nb[q].y = (R(2) * hi - b2[q].y) + (ck.x * ps[q].y + ck.y * ps[q].x);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const uint32_t e = q * NT + threadIdx.x;
+                if (e < N) {
+                    b2[q] = b1[q];
+                    b1[q] = nb[q];
+                    lds[e] = nb[q];
+                }
+            }
+            __syncthreads();
+        }
+        const C c0 = I.coef[0];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t e = q * NT + threadIdx.x;
+            if (e < N) {
+                C y;
+                if (I.K == 0) {
+                    y.x = c0.x * ps[q].x - c0.y * ps[q].y;
+                    y.y = c0.x * ps[q].y + c0.y * ps[q].x;
+                } else {
+                    R sr = R(0), si = R(0);
+                    for (int j = 0; j < I.n; ++j) {
+                        const C x = lds[e ^ (1u << j)];
+                        sr += x.x;
+                        si += x.y;
+                    }
+                    const R hr = dd[q] * b1[q].x + I.g * sr;
+                    const R hi = dd[q] * b1[q].y + I.g * si;
+                    y.x = (hr - b2[q].x) + (c0.x * ps[q].x - c0.y * ps[q].y);
+                    y.y = (hi - b2[q].y) + (c0.x * ps[q].y + c0.y * ps[q].x);
+                }
+                C o;
+                o.x = I.pr * y.x - I.pi * y.y;
+                o.y = I.pr * y.y + I.pi * y.x;
+                I.out[e] = o;
+            }
+        }
+        __syncthreads();  // lds is reused by the next instance
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+static inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct WsLayout {
+    size_t b1, b2, d, part, red, hj, q, qt, coef, items, total;
+};
+
+static WsLayout ws_layout(int n, int prec, bool otf)
+{
+    const size_t N = size_t(1) << n;
+    const size_t cs = (prec == 64) ? 8 : 16, rs = (prec == 64) ? 4 : 8;
+    WsLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+    L.b1 = take(N * cs);
+    L.b2 = take(N * cs);
+    L.d = otf ? size_t(-1) : take(N * rs);
+    L.part = take(2 * MAXPART * sizeof(double));
+    L.red = take(2 * sizeof(double));
+    L.hj = take((32 + 32 * 31 / 2) * sizeof(double));
+    L.q = take((size_t(1) << LB_TAB) * sizeof(double));
+    L.qt = take((size_t(1) << LB_TAB) * sizeof(float));
+    L.coef = (n <= Cfg<float>::TB) ? take((size_t)(KMAX_ONCHIP + 1) * cs) : size_t(-1);
+    L.items = take(256);
+    L.total = off;
+    return L;
+}
+
+struct PassPlan { int L, g0, h; };
+
+template <typename R>
+static std::vector<PassPlan> plan_passes(int n)
+{
+    constexpr int TB = Cfg<R>::TB, LMIN = Cfg<R>::LMIN;
+    std::vector<PassPlan> P;
+    const int h0 = std::min(n, TB);
+    P.push_back({0, 0, h0});
+    const int rem = n - h0;
+    if (rem > 0) {
+        const int cap = TB - LMIN;
+        const int np = (rem + cap - 1) / cap;
+        int g = h0;
+        for (int p = 0; p < np; ++p) {
+            const int hh = rem / np + (p < rem % np ? 1 : 0);
+            P.push_back({TB - hh, g, hh});
+            g += hh;
+        }
+    }
+    return P;
+}
+
+#define QW_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            set_error(std::string(#call) + ": " + hipGetErrorString(e_));              \
+            return QW_EHIP;                                                            \
+        }                                                                              \
+    } while (0)
+
+static inline int grid_for(uint64_t work, int per_block, int cap)
+{
+    uint64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (uint64_t)cap) g = cap;
+    return (int)g;
+}
+
+template <typename R> static constexpr int prec_of() { return sizeof(R) == 4 ? 64 : 128; }
+
+// Upload h, J, build the Q table; returns the tables view.
+static qw_status setup_tables(int n, const double *h, const double *J, char *ws, const WsLayout &L,
+                              hipStream_t s, EnergyTables *T)
+{
+    const int np = n * (n - 1) / 2;
+    std::vector<double> hj(n + np);
+    std::memcpy(hj.data(), h, n * sizeof(double));
+    if (np) std::memcpy(hj.data() + n, J, np * sizeof(double));
+    double *dhj = reinterpret_cast<double *>(ws + L.hj);
+    QW_HIP(hipMemcpyAsync(dhj, hj.data(), hj.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    T->h = dhj;
+    T->J = dhj + n;
+    T->Q = reinterpret_cast<double *>(ws + L.q);
+    T->n = n;
+    T->LB = std::min(n, LB_TAB);
+    const int nq = 1 << T->LB;
+    hipLaunchKernelGGL(k_qtable, dim3((nq + 255) / 256), dim3(256), 0, s, *T, const_cast<double *>(T->Q));
+    QW_HIP(hipGetLastError());
+    QW_HIP(hipStreamSynchronize(s));  // hj lives on this stack frame
+    return QW_OK;
+}
+
+template <typename R>
+static qw_status minmax(int n, const R *diag, const EnergyTables *T, char *ws, const WsLayout &L,
+                        hipStream_t s, double *emin, double *emax)
+{
+    double *part = reinterpret_cast<double *>(ws + L.part);
+    double *red = reinterpret_cast<double *>(ws + L.red);
+    int np;
+    if (diag) {
+        const uint64_t N = uint64_t(1) << n;
+        np = grid_for(N, 256 * 16, MAXPART);
+        hipLaunchKernelGGL(k_minmax_diag<R>, dim3(np), dim3(256), 0, s, diag, N, part);
+    } else {
+        const uint64_t ntiles = uint64_t(1) << (n - T->LB);
+        np = grid_for(ntiles, 1, MAXPART);
+        hipLaunchKernelGGL(k_minmax_energy, dim3(np), dim3(256), 0, s, *T, part);
+    }
+    QW_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(256), 0, s, part, np, red);
+    QW_HIP(hipGetLastError());
+    double h2[2];
+    QW_HIP(hipMemcpyAsync(h2, red, sizeof(h2), hipMemcpyDeviceToHost, s));
+    QW_HIP(hipStreamSynchronize(s));
+    *emin = h2[0];
+    *emax = h2[1];
+    return QW_OK;
+}
+
+static bool finite(double x) { return std::isfinite(x); }
+
+template <typename R>
+static qw_status validate(int n, const R *diag, const double *h, const double *J, double gamma, double t,
+                          const void *psi_in, const void *psi_out, double tol, int method, void *ws)
+{
+    if (n < 1 || n > 32) { set_error("n must be in 1..32"); return QW_EINVAL; }
+    if (!finite(gamma) || !finite(t)) { set_error("gamma and t must be finite"); return QW_EINVAL; }
+    if (!(tol > 0.0) || !finite(tol)) { set_error("tol must be positive and finite"); return QW_EINVAL; }
+    if (method != QW_CHEB && method != QW_CF) { set_error("unknown method"); return QW_EINVAL; }
+    if (!psi_in || !psi_out) { set_error("psi_in and psi_out are required"); return QW_EINVAL; }
+    if (!ws) { set_error("workspace is required"); return QW_EINVAL; }
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) { set_error("workspace must be 256-byte aligned"); return QW_EINVAL; }
+    if ((reinterpret_cast<uintptr_t>(psi_in) & 15) != 0 || (reinterpret_cast<uintptr_t>(psi_out) & 15) != 0) {
+        set_error("state vectors must be 16-byte aligned");
+        return QW_EINVAL;
+    }
+    if (!diag) {
+        if (!h || (n > 1 && !J)) { set_error("diag == NULL requires h and J"); return QW_EINVAL; }
+        for (int j = 0; j < n; ++j)
+            if (!finite(h[j])) { set_error("h has a non-finite entry"); return QW_EINVAL; }
+        for (int p = 0; p < n * (n - 1) / 2; ++p)
+            if (!finite(J[p])) { set_error("J has a non-finite entry"); return QW_EINVAL; }
+    }
+    return QW_OK;
+}
+
+// Spectral shift / bound, optionally uploading tables.  Leaves T valid when
+// diag == NULL.
+template <typename R>
+static qw_status bound_impl(int n, const R *diag, const double *h, const double *J, double gamma,
+                            char *ws, const WsLayout &L, hipStream_t s, EnergyTables *T,
+                            double *c, double *r)
+{
+    if (!diag) {
+        qw_status st = setup_tables(n, h, J, ws, L, s, T);
+        if (st != QW_OK) return st;
+    }
+    double emin, emax;
+    qw_status st = minmax<R>(n, diag, T, ws, L, s, &emin, &emax);
+    if (st != QW_OK) return st;
+    if (!finite(emin) || !finite(emax)) { set_error("diagonal has non-finite entries"); return QW_EINVAL; }
+    *c = 0.5 * (emax + emin);
+    *r = 0.5 * (emax - emin) + n * std::fabs(gamma);
+    return QW_OK;
+}
+
+template <typename R>
+static void launch_pass(const PassArgs<R> &a, bool start, bool otf, uint64_t ntiles, hipStream_t s)
+{
+    constexpr int TB = Cfg<R>::TB, NT = Cfg<R>::NT;
+    if (start) {
+        if constexpr (sizeof(R) == 4) {
+            if (otf) {
+                hipLaunchKernelGGL((k_pass<R, TB, NT, true, true>), dim3((unsigned)ntiles), dim3(NT), 0, s, a);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_pass<R, TB, NT, true, false>), dim3((unsigned)ntiles), dim3(NT), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_pass<R, TB, NT, false, false>), dim3((unsigned)ntiles), dim3(NT), 0, s, a);
+    }
+}
+
+template <typename R>
+static qw_status action_impl(int n, const R *diag, const double *h, const double *J, double gamma, double t,
+                             const void *psi_in, void *psi_out, double tol, int method, void *workspace,
+                             size_t ws_bytes, void *stream, qw_info *info)
+{
+    using C = typename Cplx<R>::T;
+    using V = CVec<R>;
+    qw_status st = validate<R>(n, diag, h, J, gamma, t, psi_in, psi_out, tol, method, workspace);
+    if (st != QW_OK) return st;
+    const bool otf = (diag == nullptr && n >= 31);
+    if (otf && sizeof(R) != 4) { set_error("the on-the-fly diagonal is implemented for complex64 only"); return QW_EINVAL; }
+    const WsLayout L = ws_layout(n, prec_of<R>(), otf);
+    if (ws_bytes < L.total) {
+        set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
+        return QW_ENOMEM;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    const uint64_t N = uint64_t(1) << n;
+
+    EnergyTables T{};
+    double c = 0.0, r = 0.0;
+    st = bound_impl<R>(n, diag, h, J, gamma, ws, L, s, &T, &c, &r);
+    if (st != QW_OK) return st;
+
+    // g = gamma / r; in single precision round g towards zero and take
+    // r = gamma / g, which is still a bound and makes g exact in float.
+    double g = (r > 0.0) ? gamma / r : 0.0;
+    if (sizeof(R) == 4 && gamma != 0.0 && r > 0.0) {
+        float gf = (float)g;
+        if (std::fabs((double)gf) > std::fabs(g)) gf = std::nextafter(gf, 0.0f);
+        g = (double)gf;
+        r = gamma / g;
+    }
+    const double inv_r = (r > 0.0) ? 1.0 / r : 0.0;
+    const double ph_r = std::cos(t * c), ph_i = -std::sin(t * c);   // exp(-i t c)
+    const uint64_t nvec = N / V::N;
+    const int eg = grid_for(nvec, 256 * 4, 1 << 16);
+
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->n = n;
+        info->shift_c = c;
+        info->radius_r = r;
+        info->method = method;
+    }
+    const C *psi = static_cast<const C *>(psi_in);
+    C *out = static_cast<C *>(psi_out);
+    if (r == 0.0) {
+        hipLaunchKernelGGL(k_scale<R>, dim3(eg), dim3(256), 0, s, reinterpret_cast<const V *>(psi),
+                           reinterpret_cast<V *>(out), (R)ph_r, (R)ph_i, nvec);
+        QW_HIP(hipGetLastError());
+        return QW_OK;
+    }
+
+    // normalised diagonal
+    R *dn = otf ? nullptr : reinterpret_cast<R *>(ws + L.d);
+    float *qt = reinterpret_cast<float *>(ws + L.qt);
+    if (!otf) {
+        if (diag) {
+            hipLaunchKernelGGL(k_normalize_diag<R>, dim3(grid_for(N, 256 * 8, 1 << 16)), dim3(256), 0, s,
+                               diag, N, c, inv_r, dn);
+        } else {
+            hipLaunchKernelGGL(k_normalize_energy<R>, dim3(grid_for(N >> T.LB, 1, 1 << 16)), dim3(256), 0, s,
+                               T, c, inv_r, dn);
+        }
+    } else {
+        hipLaunchKernelGGL(k_qtilde, dim3((1 << LB_TAB) / 256), dim3(256), 0, s, T.Q, LB_TAB, inv_r, qt);
+    }
+    QW_HIP(hipGetLastError());
+
+    // coefficients (host, double)
+    const double a = t * r;
+    std::vector<double> alpha;
+    int K = 0;
+    double err = 0.0;
+    if (coefficients(a, tol, method, alpha, &K, &err) != 0) {
+        set_error("coefficient setup failed");
+        return QW_ENOCONV;
+    }
+    auto coef_of = [&](int k, double &cr, double &ci) {
+        const double al = alpha[k];
+        switch (k & 3) {
+        case 0: cr = al; ci = 0.0; break;
+        case 1: cr = 0.0; ci = -al; break;
+        case 2: cr = -al; ci = 0.0; break;
+        default: cr = 0.0; ci = al; break;
+        }
+    };
+    const std::vector<PassPlan> plan = plan_passes<R>(n);
+    if (info) {
+        info->K = K;
+        info->a = a;
+        info->trunc_bound = err;
+        info->passes = (n <= Cfg<R>::TB) ? 1 : (int)plan.size();
+    }
+
+    if (n <= Cfg<R>::TB) {
+        // on-chip: whole recurrence in one workgroup
+        if (K > KMAX_ONCHIP) { set_error("degree too large for the on-chip path"); return QW_ENOMEM; }
+        std::vector<C> ch(K + 1);
+        for (int k = 0; k <= K; ++k) {
+            double cr, ci;
+            coef_of(k, cr, ci);
+            ch[k].x = (R)cr;
+            ch[k].y = (R)ci;
+        }
+        C *dcoef = reinterpret_cast<C *>(ws + L.coef);
+        OnchipItem<R> item{psi, out, dn, dcoef, (R)g, (R)ph_r, (R)ph_i, n, K};
+        OnchipItem<R> *ditem = reinterpret_cast<OnchipItem<R> *>(ws + L.items);
+        QW_HIP(hipMemcpyAsync(dcoef, ch.data(), ch.size() * sizeof(C), hipMemcpyHostToDevice, s));
+        QW_HIP(hipMemcpyAsync(ditem, &item, sizeof(item), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL((k_onchip<R, Cfg<R>::TB, ONCHIP_NT>), dim3(1), dim3(ONCHIP_NT), 0, s,
+                           (const OnchipItem<R> *)ditem, (const int *)nullptr, 1);
+        QW_HIP(hipGetLastError());
+        QW_HIP(hipStreamSynchronize(s));  // host copies of ch/item go out of scope
+        return QW_OK;
+    }
+
+    if (K == 0) {
+        double cr, ci;
+        coef_of(0, cr, ci);
+        const double pr = cr * ph_r - ci * ph_i, pi = cr * ph_i + ci * ph_r;
+        hipLaunchKernelGGL(k_scale<R>, dim3(eg), dim3(256), 0, s, reinterpret_cast<const V *>(psi),
+                           reinterpret_cast<V *>(out), (R)pr, (R)pi, nvec);
+        QW_HIP(hipGetLastError());
+        return QW_OK;
+    }
+
+    C *B1 = reinterpret_cast<C *>(ws + L.b1);
+    C *B2 = reinterpret_cast<C *>(ws + L.b2);
+    {
+        double cr, ci;
+        coef_of(K, cr, ci);
+        hipLaunchKernelGGL(k_init<R>, dim3(eg), dim3(256), 0, s, reinterpret_cast<const V *>(psi),
+                           reinterpret_cast<V *>(B1), reinterpret_cast<V *>(B2), (R)cr, (R)ci, nvec);
+        QW_HIP(hipGetLastError());
+    }
+    PassArgs<R> pa{};
+    pa.psi = psi;
+    pa.d = dn;
+    pa.Qt = qt;
+    pa.hJ = T.h;
+    pa.otf_c = c;
+    pa.otf_inv_r = inv_r;
+    pa.g = (R)g;
+    pa.n = n;
+    const int P = (int)plan.size();
+    for (int k = K - 1; k >= 0; --k) {
+        double cr, ci;
+        coef_of(k, cr, ci);
+        const bool fin = (k == 0);
+        for (int p = 0; p < P; ++p) {
+            pa.b1 = B1;
+            pa.acc = B2;
+            const bool last = (p == P - 1);
+            pa.dst = (fin && last) ? out : B2;
+            pa.scale = fin ? R(1) : R(2);
+            pa.cr = (R)cr;
+            pa.ci = (R)ci;
+            pa.pr = (fin && last) ? (R)ph_r : R(1);
+            pa.pi = (fin && last) ? (R)ph_i : R(0);
+            pa.L = plan[p].L;
+            pa.g0 = plan[p].g0;
+            pa.h = plan[p].h;
+            const uint64_t ntiles = N >> (plan[p].L + plan[p].h);
+            launch_pass<R>(pa, p == 0, otf, ntiles, s);
+        }
+        QW_HIP(hipGetLastError());
+        std::swap(B1, B2);
+    }
+    return QW_OK;
+}
+
+template <typename R>
+static qw_status bound_entry(int n, const R *diag, const double *h, const double *J, double gamma,
+                             double *c, double *r, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (n < 1 || n > 32 || !c || !r || !workspace || !finite(gamma)) { set_error("bad arguments"); return QW_EINVAL; }
+    if (!diag && (!h || (n > 1 && !J))) { set_error("diag == NULL requires h and J"); return QW_EINVAL; }
+    const WsLayout L = ws_layout(n, prec_of<R>(), diag == nullptr && n >= 31);
+    if (ws_bytes < L.total) { set_error("workspace too small"); return QW_ENOMEM; }
+    EnergyTables T{};
+    return bound_impl<R>(n, diag, h, J, gamma, static_cast<char *>(workspace), L,
+                         reinterpret_cast<hipStream_t>(stream), &T, c, r);
+}
+
+// Host-side check of a pass plan's index map (used by the CPU tests): every
+// (tile, element) pair must hit each index of [0, 2^n) exactly once and every
+// flipped partner must stay inside the tile.
+int check_plan(int n, int prec)
+{
+    std::vector<PassPlan> plan = (prec == 64) ? plan_passes<float>(n) : plan_passes<double>(n);
+    const uint64_t N = uint64_t(1) << n;
+    const int TB = (prec == 64) ? Cfg<float>::TB : Cfg<double>::TB;
+    int covered_bits = 0;
+    for (const PassPlan &p : plan) {
+        if (p.L + p.h > TB || p.L + p.h > n) return -1;
+        if (p.L > p.g0 && p.g0 != 0) return -2;
+        std::vector<uint8_t> seen(N, 0);
+        const uint64_t ntiles = N >> (p.L + p.h);
+        const uint32_t TE = 1u << (p.L + p.h);
+        for (uint64_t t = 0; t < ntiles; ++t) {
+            const uint64_t base = tile_base(t, p.L, p.g0, p.h);
+            for (uint32_t e = 0; e < TE; ++e) {
+                const uint64_t idx = tile_index(base, e, p.L, p.g0);
+                if (idx >= N || seen[idx]) return -3;
+                seen[idx] = 1;
+                for (int j = 0; j < p.h; ++j) {
+                    const uint32_t pe = e ^ (1u << (p.L + j));
+                    if (pe >= TE) return -4;
+                    if (tile_index(base, pe, p.L, p.g0) != (idx ^ (uint64_t(1) << (p.g0 + j)))) return -5;
+                }
+            }
+        }
+        covered_bits += p.h;
+    }
+    return covered_bits == n ? (int)plan.size() : -6;
+}
+
+}  // namespace qw
+
+using namespace qw;
+
+extern "C" {
+
+const char *qw_last_error(void) { return g_err.c_str(); }
+const char *qw_version(void) { return "qwexp 0.1 (gfx950)"; }
+
+size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
+{
+    if (n < 1 || n > 32 || (precision != 64 && precision != 128)) return 0;
+    return ws_layout(n, precision, on_the_fly != 0).total;
+}
+
+qw_status qw_bessel_j(double a, int mmax, double *J)
+{
+    if (!J || mmax < 0 || !std::isfinite(a)) { set_error("bad arguments"); return QW_EINVAL; }
+    return bessel_miller(a, mmax, J) == 0 ? QW_OK : QW_EINVAL;
+}
+
+qw_status qw_cheb_coeffs(double a, double tol, qw_method method, int kmax, double *alpha, int *K_out, double *err)
+{
+    if (!alpha || !K_out || kmax < 0) { set_error("bad arguments"); return QW_EINVAL; }
+    if (!std::isfinite(a) || !(tol > 0.0) || !std::isfinite(tol)) { set_error("a must be finite and tol > 0"); return QW_EINVAL; }
+    if (method != QW_CHEB && method != QW_CF) { set_error("unknown method"); return QW_EINVAL; }
+    std::vector<double> al;
+    int K = 0;
+    double e = 0.0;
+    if (coefficients(a, tol, (int)method, al, &K, &e) != 0) { set_error("coefficient setup failed"); return QW_ENOCONV; }
+    *K_out = K;
+    if (err) *err = e;
+    if (K > kmax) { set_error("kmax too small"); return QW_ENOMEM; }
+    std::memcpy(alpha, al.data(), (K + 1) * sizeof(double));
+    return QW_OK;
+}
+
+qw_status qw_spectral_bound_f32(int n, const float *diag, const double *h, const double *J, double gamma,
+                                double *c, double *r, void *workspace, size_t ws_bytes, void *stream)
+{
+    return bound_entry<float>(n, diag, h, J, gamma, c, r, workspace, ws_bytes, stream);
+}
+
+qw_status qw_spectral_bound_f64(int n, const double *diag, const double *h, const double *J, double gamma,
+                                double *c, double *r, void *workspace, size_t ws_bytes, void *stream)
+{
+    return bound_entry<double>(n, diag, h, J, gamma, c, r, workspace, ws_bytes, stream);
+}
+
+qw_status qw_expm_action_c64(int n, const float *diag, const double *h, const double *J, double gamma, double t,
+                             const void *psi_in, void *psi_out, double tol, qw_method method, void *workspace,
+                             size_t ws_bytes, void *stream, qw_info *info)
+{
+    return action_impl<float>(n, diag, h, J, gamma, t, psi_in, psi_out, tol, (int)method, workspace, ws_bytes,
+                              stream, info);
+}
+
+qw_status qw_expm_action_c128(int n, const double *diag, const double *h, const double *J, double gamma, double t,
+                              const void *psi_in, void *psi_out, double tol, qw_method method, void *workspace,
+                              size_t ws_bytes, void *stream, qw_info *info)
+{
+    return action_impl<double>(n, diag, h, J, gamma, t, psi_in, psi_out, tol, (int)method, workspace, ws_bytes,
+                               stream, info);
+}
+
+// Host-only self check of the pass index maps; returns the number of passes or
+// a negative code.  Exported for the CPU test-suite.
+int qw_debug_check_plan(int n, int precision) { return check_plan(n, precision); }
+
+}  // extern "C"

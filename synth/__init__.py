@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "n_pairs", "pair_index", "sk_instance", "plus_state", "random_state",
     "product_state_factors", "product_state", "basis_state",
-    "batch_instances", "anneal_schedule",
+    "batch_instances", "anneal_schedule", "product_state_torch", "plus_state_torch",
 ]
 
 
@@ -105,3 +105,20 @@ def anneal_schedule(S: int = 16, g_start: float = 2.0, g_end: float = 0.05,
     gam = np.linspace(g_start, g_end, S)
     ts = np.full(S, t_seg)
     return gam.astype(np.float64), ts.astype(np.float64)
+
+
+def product_state_torch(factors: np.ndarray, device, dtype):
+    """Device copy of product_state(factors): the Kronecker product built on the
+    GPU one qubit at a time (qubit j = bit j), for sizes too large for the host."""
+    import torch
+    f = torch.as_tensor(np.asarray(factors), dtype=torch.complex128, device=device)
+    psi = f[0].clone()
+    for j in range(1, f.shape[0]):
+        psi = torch.kron(f[j], psi)     # new qubit becomes the most significant bit
+    return psi.to(dtype).contiguous()
+
+
+def plus_state_torch(n: int, device, dtype):
+    import torch
+    N = 1 << n
+    return torch.full((N,), 1.0 / np.sqrt(N), dtype=dtype, device=device)

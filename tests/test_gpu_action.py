@@ -1,0 +1,243 @@
+"""GPU parity of qw_expm_action_{c64,c128} against the CPU oracle.
+
+Element-by-element comparisons (relative L2 over the whole vector) at sizes the
+oracle finishes in seconds, spanning the on-chip path (n <= 13), two passes per
+term (n = 14..22 in complex64) and three (n >= 23); at the full 28-qubit
+workload, properties that hold at any size and closed forms evaluated one
+sampled amplitude at a time.
+
+Tolerances: complex128 <= 1e-12 against the oracle run at the same truncation
+tolerance (identical degree K), complex64 <= 1e-5 against the oracle at 1e-13.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+C64_TOL = 1e-5
+C128_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2608_12058_amd as qw
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    qw.lib()
+    return torch, qw
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _run(env, n, psi_np, gamma, t, tol, prec, method="cheb", diag_np=None, h=None, J=None, inplace=False):
+    torch, qw = env
+    cdt = torch.complex64 if prec == 64 else torch.complex128
+    rdt = torch.float32 if prec == 64 else torch.float64
+    psi = torch.as_tensor(psi_np).to(cdt).cuda()
+    diag = torch.as_tensor(diag_np).to(rdt).cuda() if diag_np is not None else None
+    out = psi if inplace else None
+    y, info = qw.expm_action(psi, gamma, t, diag=diag, h=h, J=J, tol=tol, method=method, out=out)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.complex128), info
+
+
+def test_config1_plain_c128_vs_eigh(env, oracle_mod):
+    """n = 10, complex128, SK seed 0, gamma = 1, t = 1, |+>, tol 1e-12."""
+    n = 10
+    h, J = synth.sk_instance(n, 0)
+    E = oracle_mod.energies(n, h, J)
+    psi = synth.plus_state(n)
+    y0 = oracle_mod.expm_action_dense(n, E, 1.0, 1.0, psi)
+    y1 = oracle_mod.expm_action(n, E, 1.0, 1.0, psi, 1e-12)
+    for kw in (dict(h=h, J=J), dict(diag_np=E)):
+        y, info = _run(env, n, psi, 1.0, 1.0, 1e-12, 128, **kw)
+        assert info["K"] == 48
+        assert rel(y, y0) <= C128_TOL
+        assert rel(y, y1) <= C128_TOL
+
+
+CASES = [
+    # n, gamma, t, seed
+    (1, 0.7, 2.0, 1),
+    (2, 1.1, 1.5, 2),
+    (5, 0.8, 3.0, 3),
+    (12, 1.0, 1.0, 4),
+    (13, 0.9, 1.3, 5),
+    (14, 1.2, 0.8, 6),
+    (17, 0.8, 1.0, 7),
+    (20, 1.0, 0.5, 8),
+    (22, 0.7, 0.4, 9),
+    (23, 1.0, 0.3, 10),
+]
+
+
+@pytest.mark.parametrize("n,gamma,t,seed", CASES)
+def test_parity_c128(env, oracle_mod, n, gamma, t, seed):
+    h, J = synth.sk_instance(n, seed)
+    E = oracle_mod.energies(n, h, J)
+    psi = synth.random_state(n, seed + 100)
+    ref = oracle_mod.expm_action(n, E, gamma, t, psi, 1e-12)
+    y, info = _run(env, n, psi, gamma, t, 1e-12, 128, h=h, J=J)
+    assert rel(y, ref) <= C128_TOL, info
+
+
+@pytest.mark.parametrize("n,gamma,t,seed", CASES)
+def test_parity_c64(env, oracle_mod, n, gamma, t, seed):
+    h, J = synth.sk_instance(n, seed)
+    E = oracle_mod.energies(n, h, J)
+    psi = synth.random_state(n, seed + 200)
+    ref = oracle_mod.expm_action(n, E, gamma, t, psi, 1e-13)
+    y, info = _run(env, n, psi, gamma, t, 2.0 ** -23, 64, h=h, J=J)
+    assert rel(y, ref) <= C64_TOL, info
+    y2, _ = _run(env, n, psi, gamma, t, 2.0 ** -23, 64, diag_np=E)
+    assert rel(y2, ref) <= C64_TOL
+
+
+@pytest.mark.parametrize("prec", [64, 128])
+def test_cf_method(env, oracle_mod, prec):
+    n = 16
+    h, J = synth.sk_instance(n, 31)
+    E = oracle_mod.energies(n, h, J)
+    psi = synth.plus_state(n)
+    tol = 2.0 ** -23 if prec == 64 else 1e-11
+    ref = oracle_mod.expm_action(n, E, 0.8, 4.0, psi, 1e-13)
+    y, info = _run(env, n, psi, 0.8, 4.0, tol, prec, method="cf", h=h, J=J)
+    assert info["method"] == 1
+    assert rel(y, ref) <= (C64_TOL if prec == 64 else 2e-11)
+    yo = oracle_mod.expm_action(n, E, 0.8, 4.0, psi, tol, method="cf")
+    if prec == 128:
+        assert rel(y, yo) <= C128_TOL
+
+
+@pytest.mark.parametrize("prec", [64, 128])
+@pytest.mark.parametrize("n", [11, 19])
+def test_in_place(env, oracle_mod, prec, n):
+    h, J = synth.sk_instance(n, 41)
+    E = oracle_mod.energies(n, h, J)
+    psi = synth.random_state(n, 41)
+    ref = oracle_mod.expm_action(n, E, 1.0, 0.7, psi, 1e-13)
+    y, _ = _run(env, n, psi, 1.0, 0.7, 1e-12 if prec == 128 else 2.0 ** -23, prec, h=h, J=J, inplace=True)
+    assert rel(y, ref) <= (C64_TOL if prec == 64 else C128_TOL)
+
+
+@pytest.mark.parametrize("prec", [64, 128])
+def test_closed_forms(env, oracle_mod, prec):
+    tol = 2.0 ** -23 if prec == 64 else 1e-12
+    bar = C64_TOL if prec == 64 else C128_TOL
+    n = 18
+    h, J = synth.sk_instance(n, 51)
+    E = oracle_mod.energies(n, h, J)
+    psi = synth.random_state(n, 51)
+    y, _ = _run(env, n, psi, 0.0, 2.5, tol, prec, h=h, J=J)
+    assert rel(y, oracle_mod.closed_form_gamma0(E, 2.5, psi)) <= bar
+    z = np.zeros(n)
+    zJ = np.zeros(n * (n - 1) // 2)
+    y, _ = _run(env, n, psi, 1.3, 2.2, tol, prec, h=z, J=zJ)
+    assert rel(y, oracle_mod.closed_form_hp0(n, 1.3, 2.2, psi)) <= bar
+
+
+@pytest.mark.parametrize("prec", [64, 128])
+def test_degenerate_cases(env, prec):
+    n = 15
+    psi = synth.random_state(n, 61)
+    h, J = synth.sk_instance(n, 61)
+    # t = 0: a = 0, K = 0, the identity
+    y, info = _run(env, n, psi, 1.0, 0.0, 1e-10, prec, h=h, J=J)
+    assert info["K"] == 0
+    assert rel(y, psi) <= (1e-7 if prec == 64 else 1e-15)
+    # H = 0 (no couplings, gamma = 0): zero bound, output = psi
+    y, info = _run(env, n, psi, 0.0, 3.0, 1e-10, prec, h=np.zeros(n), J=np.zeros(n * (n - 1) // 2))
+    assert info["radius_r"] == 0.0
+    assert rel(y, psi) <= (1e-7 if prec == 64 else 1e-15)
+    # constant diagonal only: a pure phase exp(-i t c)
+    Ec = np.full(1 << n, 0.37)
+    y, info = _run(env, n, psi, 0.0, 3.0, 1e-10, prec, diag_np=Ec)
+    assert rel(y, np.exp(-1j * 3.0 * 0.37) * psi) <= (1e-6 if prec == 64 else 1e-14)
+
+
+def test_spectral_bound_matches_oracle(env, oracle_mod):
+    torch, qw = env
+    n = 20
+    h, J = synth.sk_instance(n, 71)
+    E = oracle_mod.energies(n, h, J)
+    c_ref, r_ref = oracle_mod.spectral_shift_radius(E, n, 0.9)
+    c, r = qw.spectral_bound(n, 0.9, h=h, J=J, precision=128)
+    assert abs(c - c_ref) < 1e-12 and abs(r - r_ref) < 1e-12
+    c, r = qw.spectral_bound(n, 0.9, diag=torch.as_tensor(E).cuda(), precision=128)
+    assert abs(c - c_ref) < 1e-12 and abs(r - r_ref) < 1e-12
+
+
+def test_deterministic(env):
+    n = 21
+    h, J = synth.sk_instance(n, 81)
+    psi = synth.plus_state(n)
+    y1, _ = _run(env, n, psi, 1.0, 1.0, 2.0 ** -23, 64, h=h, J=J)
+    y2, _ = _run(env, n, psi, 1.0, 1.0, 2.0 ** -23, 64, h=h, J=J)
+    assert np.array_equal(y1, y2)
+
+
+# ------------------------------------------------------------ full size (28 qubits)
+
+N28 = 28
+
+
+def test_n28_time_reversal_and_norm(env):
+    """SK seed 0, gamma = 1, t = 5, |+> (the benchmark workload, same launch
+    configuration): U(-t) U(t) psi = psi and the norm is conserved."""
+    torch, qw = env
+    h, J = synth.sk_instance(N28, 0)
+    psi = synth.plus_state_torch(N28, "cuda", torch.complex64)
+    y, info = qw.expm_action(psi, 1.0, 5.0, h=h, J=J, tol=2.0 ** -23)
+    assert info["passes"] == 3
+    nrm = torch.linalg.vector_norm(y.to(torch.complex128)).item()
+    assert abs(nrm - 1.0) < 1e-5
+    back, _ = qw.expm_action(y, 1.0, -5.0, h=h, J=J, tol=2.0 ** -23)
+    err = (torch.linalg.vector_norm((back - psi).to(torch.complex128)) /
+           torch.linalg.vector_norm(psi.to(torch.complex128))).item()
+    assert err < 2 * C64_TOL
+    del y, back
+    torch.cuda.empty_cache()
+
+
+def test_n28_c64_matches_c128(env):
+    torch, qw = env
+    h, J = synth.sk_instance(N28, 0)
+    psi = synth.plus_state_torch(N28, "cuda", torch.complex128)
+    y128, _ = qw.expm_action(psi, 1.0, 5.0, h=h, J=J, tol=1e-12)
+    y64, _ = qw.expm_action(psi.to(torch.complex64), 1.0, 5.0, h=h, J=J, tol=2.0 ** -23)
+    err = (torch.linalg.vector_norm(y64.to(torch.complex128) - y128) / torch.linalg.vector_norm(y128)).item()
+    assert err < C64_TOL
+    del y128, y64, psi
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", [64, 128])
+def test_n28_sampled_closed_forms(env, oracle_mod, prec):
+    """H_P = 0 on a random product state, and gamma = 0 on |+>, checked at 4096
+    sampled amplitudes computed one by one by the oracle."""
+    torch, qw = env
+    cdt = torch.complex64 if prec == 64 else torch.complex128
+    tol = 2.0 ** -23 if prec == 64 else 1e-12
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([[0, (1 << N28) - 1], rng.integers(0, 1 << N28, 4094)])
+    f = synth.product_state_factors(N28, 17)
+    psi = synth.product_state_torch(f, "cuda", cdt)
+    zh, zJ = np.zeros(N28), np.zeros(N28 * (N28 - 1) // 2)
+    y, _ = qw.expm_action(psi, 0.9, 2.0, h=zh, J=zJ, tol=tol)
+    got = y[torch.as_tensor(idx, device="cuda")].cpu().numpy().astype(np.complex128)
+    ref = oracle_mod.closed_form_hp0_product_amps(f, 0.9, 2.0, idx)
+    assert rel(got, ref) <= (C64_TOL if prec == 64 else C128_TOL)
+    del y, psi
+    h, J = synth.sk_instance(N28, 0)
+    psi = synth.plus_state_torch(N28, "cuda", cdt)
+    y, _ = qw.expm_action(psi, 0.0, 5.0, h=h, J=J, tol=tol)
+    got = y[torch.as_tensor(idx[:512], device="cuda")].cpu().numpy().astype(np.complex128)
+    amp = np.full(512, 1.0 / np.sqrt(1 << N28), dtype=np.complex128)
+    ref = oracle_mod.closed_form_gamma0_amps(N28, h, J, 5.0, amp, idx[:512])
+    assert rel(got, ref) <= (C64_TOL if prec == 64 else C128_TOL)
+    del y, psi
+    torch.cuda.empty_cache()
