@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark of psi(t) = exp(-i t H) psi on one MI355X.
+
+Workload (one "step"): one complete qw_expm_action_c64 call -- spectral bound
+and normalised diagonal generated on the GPU from the SK couplings, Bessel
+coefficients on the host, the Clenshaw recurrence on the GPU -- for the
+28-qubit SK instance of seed 0 (J_jk ~ N(0, 1/n), h_j ~ N(0, 1)), gamma = 1,
+t = 5, truncation tolerance 2^-23, psi0 = |+>^28, complex64 state with a float
+diagonal.  Inputs are resident in HBM before the timed region.
+
+Reported: amplitude-terms per second (N * K / step time), the HBM roofline of
+the Clenshaw term (36 algorithmic bytes per amplitude and term, measured with
+HIP events on the launch stream), the same workload in complex128 for the
+fp32-vs-fp64 comparison, and the CPU oracle timed on a bounded sample of the
+same recurrence on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
+
+METRIC = "n=28 exp(-itH)ψ: amps·terms/s, HBM GB/s % peak; fp32/batched/grad vs fp64 plain"
+UNIT = "amps·terms/s"
+PEAK_HBM_GBPS = 8000.0
+BYTES_PER_AMP_TERM = {64: 36, 128: 72}     # algorithmic bytes per amplitude and term
+BYTES_INIT = {64: 24, 128: 48}             # b_K = c_K psi, b_{K+1} = 0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=28, help="qubits (default: the 28-qubit headline workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c128", action="store_true")
+    ap.add_argument("--cpu-terms", type=int, default=30, help="Clenshaw terms of the CPU oracle sample")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 2 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic_n28_c64.json"),
+                    help="HBM bytes per term measured with rocprofv3 counters (optional)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n, h, J, gamma, t, tol, terms):
+    """The oracle (plain C loops, complex128, OpenMP) on a sample of the same
+    recurrence: the first `terms` Clenshaw terms of the same instance."""
+    import numpy as np
+    import oracle
+    E = oracle.energies(n, h, J)
+    c, r = oracle.spectral_shift_radius(E, n, gamma)
+    d = E
+    d -= c
+    d /= r
+    del E
+    coef = oracle.cheb_coeffs(t * r, tol)
+    v = np.full(1 << n, 1.0 / np.sqrt(1 << n), dtype=np.complex128)
+    sec = oracle.time_clenshaw_terms(n, coef, d, gamma / r, v, terms)
+    return {"value": (1 << n) * terms / sec, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{terms} Clenshaw terms of the same {n}-qubit instance, complex128 plain C loops "
+                      f"({sec:.1f} s)"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
+              "the hot path here is the single-GPU kernel; multi-GPU sharding is described in DESIGN.md "
+              "but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2608_12058_amd as qw
+    import synth
+
+    n, gamma, t, tol = args.n, 1.0, 5.0, 2.0 ** -23
+    N = 1 << n
+    h, J = synth.sk_instance(n, 0)
+    dev = torch.device("cuda", 0)
+    psi = synth.plus_state_torch(n, dev, torch.complex64)
+    out = torch.empty_like(psi)
+    ws = qw.Workspace.for_problem(n, 64, device=dev)
+    torch.cuda.synchronize()
+
+    def step(timing=0):
+        return qw.expm_action(psi, gamma, t, h=h, J=J, tol=tol, out=out, workspace=ws, timing=timing)[1]
+
+    log(f"[bench] n={n} warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(step(timing=1))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    K = infos[0]["K"]
+    P = infos[0]["passes"]
+    loop_ms = float(np.median([i["loop_ms"] for i in infos]))
+    setup_ms = float(np.median([i["setup_ms"] for i in infos]))
+    value = N * K / (ms_step * 1e-3)
+
+    # per-pass live durations (one extra untimed call with an event after every pass)
+    pinfo = step(timing=2)
+    pass_ms = pinfo["pass_ms"][:P]
+    terms = K  # K-1 recurrence terms + the final step, each P passes
+    term_ms = loop_ms / terms
+    alg_bytes_term = BYTES_PER_AMP_TERM[64] * N
+    achieved = (BYTES_INIT[64] * N + alg_bytes_term * terms) / (loop_ms * 1e-3) / 1e9
+    pass_bytes = [36 * N] + [24 * N] * (P - 1)      # bytes each pass actually moves
+    passes = [{"pass": p, "avg_us": pass_ms[p] / terms * 1e3, "moved_bytes": pass_bytes[p],
+               "moved_GBps": pass_bytes[p] / (pass_ms[p] / terms * 1e-3) / 1e9} for p in range(P)]
+
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            with open(args.traffic_json) as f:
+                tj = json.load(f)
+            if tj.get("kernel_version") == qw.version() and tj.get("n") == n:
+                traffic = tj.get("bytes_per_term")
+        except Exception:
+            traffic = None
+
+    result = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": f"SK spin glass n={n} (seed 0, J~N(0,1/n), h~N(0,1)), gamma=1, t=5, "
+                               f"tol=2^-23, psi0=|+>, complex64 state, fp32 diagonal generated on GPU",
+                   "n": n, "K": K, "passes_per_term": P, "radius_r": infos[0]["radius_r"],
+                   "a": infos[0]["a"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBPS, "traffic": traffic,
+                     "kernel": "Clenshaw term (all passes), 36 B/amp algorithmic",
+                     "avg_term_us": term_ms * 1e3},
+        "loop_ms": loop_ms, "setup_ms": setup_ms,
+        "loop_amp_terms_per_s": N * K / (loop_ms * 1e-3),
+        "passes": passes,
+    }
+
+    if not args.no_c128:
+        log("[bench] complex128 comparison")
+        del out
+        ws128 = qw.Workspace.for_problem(n, 128, device=dev)
+        psi128 = psi.to(torch.complex128)
+        out128 = torch.empty_like(psi128)
+        qw.expm_action(psi128, gamma, t, h=h, J=J, tol=1e-12, out=out128, workspace=ws128)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        i128 = qw.expm_action(psi128, gamma, t, h=h, J=J, tol=1e-12, out=out128, workspace=ws128, timing=1)[1]
+        tb = time.perf_counter()
+        result["c128_plain"] = {"tol": 1e-12, "K": i128["K"], "ms_per_call": (tb - ta) * 1e3,
+                                "loop_ms": i128["loop_ms"],
+                                "value": N * i128["K"] / (tb - ta),
+                                "hbm_GBps_alg": (BYTES_INIT[128] + BYTES_PER_AMP_TERM[128] * i128["K"]) * N
+                                / (i128["loop_ms"] * 1e-3) / 1e9}
+        result["c64_vs_c128_time_ratio"] = (tb - ta) * 1e3 / ms_step
+        del ws128, psi128, out128
+        torch.cuda.empty_cache()
+
+    if args.calib_copy:
+        log("[bench] calibration copy (2 GiB)")
+        a = torch.empty(1 << 31, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(n, h, J, gamma, t, tol, args.cpu_terms)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -45,7 +45,8 @@ typedef enum {
 
 typedef enum { QW_CHEB = 0, QW_CF = 1 } qw_method;
 
-/* Filled on the host before an action call returns (may be NULL). */
+/* Filled on the host before an action call returns (may be NULL).  The only
+ * input field is `timing`; every other field is output. */
 typedef struct {
     int n;              /* qubits                                                 */
     int K;              /* polynomial degree; K+1 coefficients                    */
@@ -56,6 +57,12 @@ typedef struct {
     double a;           /* t * r, the argument of the Bessel coefficients         */
     double trunc_bound; /* truncation bound (Chebyshev tail sum or CF estimate)   */
     double eval_bound;  /* a-priori evaluation-error bound, section II.B.3        */
+    int timing;         /* in: 1 records HIP events on the stream around the setup
+                           and the Clenshaw loop and synchronises at the end;
+                           2 also records one after every pass (multi-pass path) */
+    float setup_ms;     /* out (timing): bound, diagonal, coefficients            */
+    float loop_ms;      /* out (timing): all Clenshaw terms and the final step    */
+    float pass_ms[4];   /* out (timing 2): pass p summed over all terms           */
 } qw_info;
 
 /* Chebyshev coefficients of exp(-i a x) on [-1, 1] (section II.B.1, Eq. cheb,

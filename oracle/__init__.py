@@ -628,3 +628,23 @@ def anneal_grad_daleckii_krein(n, h, J, gammas, ts, psi0):
             w = spins[j] * spins[k]
             dJ.append(dE([np.diag(w)] * S, w))
     return energy, dict(gamma=dgam, t=dt, h=dh, J=np.array(dJ))
+
+
+def time_clenshaw_terms(n: int, coef: np.ndarray, d: np.ndarray, g: float, v: np.ndarray,
+                        terms: int) -> float:
+    """Wall-clock seconds of `terms` plain Clenshaw steps (the recurrence loop of
+    ``clenshaw``, in place, complex128) starting from b_K = c_K v, b_{K+1} = 0.
+    Used only for the CPU baseline of the benchmark."""
+    import time
+    lib = _load()
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    K = len(coef) - 1
+    terms = min(terms, K - 1)
+    b1 = (coef[K] * v).astype(np.complex128)
+    b2 = np.zeros_like(b1)
+    t0 = time.perf_counter()
+    for k in range(K - 1, K - 1 - terms, -1):
+        lib.orc_clenshaw_step(n, _p(d), float(g), float(coef[k].real), float(coef[k].imag),
+                              _p(v), _p(b1), _p(b2), _p(b2))
+        b1, b2 = b2, b1
+    return time.perf_counter() - t0

@@ -33,10 +33,14 @@ class QwError(RuntimeError):
 class QwInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("K", ctypes.c_int), ("passes", ctypes.c_int), ("method", ctypes.c_int),
                 ("shift_c", ctypes.c_double), ("radius_r", ctypes.c_double), ("a", ctypes.c_double),
-                ("trunc_bound", ctypes.c_double), ("eval_bound", ctypes.c_double)]
+                ("trunc_bound", ctypes.c_double), ("eval_bound", ctypes.c_double),
+                ("timing", ctypes.c_int), ("setup_ms", ctypes.c_float), ("loop_ms", ctypes.c_float),
+                ("pass_ms", ctypes.c_float * 4)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["pass_ms"] = list(self.pass_ms)
+        return d
 
 
 _lib = None
@@ -177,13 +181,16 @@ def spectral_bound(n: int, gamma: float, diag=None, h=None, J=None, precision: i
 
 
 def expm_action(psi, gamma: float, t: float, *, diag=None, h=None, J=None, tol: float = 2.0 ** -23,
-                method: str = "cheb", out=None, workspace: Workspace | None = None, stream=None):
+                method: str = "cheb", out=None, workspace: Workspace | None = None, stream=None,
+                timing: int = 0):
     """psi(t) = exp(-i t (diag(E) + gamma sum_j X_j)) psi on the GPU.
 
     psi: contiguous complex64 or complex128 CUDA tensor of length 2^n.
     diag: CUDA tensor of 2^n energies (float32 for complex64, float64 for
     complex128) or None with h (n values) and J (n(n-1)/2 values, packed upper
-    triangle) given as host arrays.  Returns (psi_out, info dict)."""
+    triangle) given as host arrays.  timing=1 records HIP events around the
+    setup and the Clenshaw loop (info["setup_ms"], info["loop_ms"]) and makes the
+    call synchronous; timing=2 also times every pass (info["pass_ms"]).  Returns (psi_out, info dict)."""
     torch = _torch()
     if not (psi.is_cuda and psi.is_contiguous() and psi.dim() == 1):
         raise ValueError("psi must be a contiguous 1-D CUDA tensor")
@@ -210,6 +217,7 @@ def expm_action(psi, gamma: float, t: float, *, diag=None, h=None, J=None, tol: 
     if workspace is None:
         workspace = Workspace.for_problem(n, prec, otf, device=psi.device)
     info = QwInfo()
+    info.timing = int(timing)
     fn = lib().qw_expm_action_c64 if prec == 64 else lib().qw_expm_action_c128
     _check(fn(int(n), _vp(diag.data_ptr()) if diag is not None else None, hp, Jp, float(gamma), float(t),
               _vp(psi.data_ptr()), _vp(out.data_ptr()), float(tol), _METHODS[method],

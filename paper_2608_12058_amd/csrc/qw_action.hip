@@ -633,6 +633,78 @@ static void launch_pass(const PassArgs<R> &a, bool start, bool otf, uint64_t nti
     }
 }
 
+// Optional HIP-event timing of an action call: mark(0) before the setup,
+// mark(1) before the Clenshaw loop, finish() after the last kernel.
+struct EventTimer {
+    bool on;
+    hipStream_t s;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    EventTimer(bool on_, hipStream_t s_) : on(on_), s(s_)
+    {
+        if (on)
+            for (auto &e : ev)
+                if (hipEventCreate(&e) != hipSuccess) on = false;
+    }
+    ~EventTimer()
+    {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    void mark(int i)
+    {
+        if (on) (void)hipEventRecord(ev[i], s);
+    }
+    qw_status finish(qw_info *info)
+    {
+        if (!on) return QW_OK;
+        QW_HIP(hipEventRecord(ev[2], s));
+        QW_HIP(hipEventSynchronize(ev[2]));
+        float a = 0.f, b = 0.f;
+        QW_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
+        QW_HIP(hipEventElapsedTime(&b, ev[1], ev[2]));
+        info->setup_ms = a;
+        info->loop_ms = b;
+        return QW_OK;
+    }
+};
+
+// timing == 2: an event after every pass; pass_ms[p] sums the durations of
+// pass p over all terms (the final step included).
+struct PassTimer {
+    bool on;
+    hipStream_t s;
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    PassTimer(bool on_, hipStream_t s_, size_t count) : on(on_), s(s_)
+    {
+        if (!on) return;
+        ev.resize(count, nullptr);
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) { on = false; break; }
+    }
+    ~PassTimer()
+    {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    void mark()
+    {
+        if (on && used < ev.size()) (void)hipEventRecord(ev[used++], s);
+    }
+    qw_status finish(qw_info *info, int P)
+    {
+        if (!on) return QW_OK;
+        QW_HIP(hipEventSynchronize(ev[used - 1]));
+        for (int p = 0; p < 4; ++p) info->pass_ms[p] = 0.f;
+        for (size_t i = 1; i < used; ++i) {
+            float ms = 0.f;
+            QW_HIP(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
+            info->pass_ms[(i - 1) % P] += ms;
+        }
+        return QW_OK;
+    }
+};
+
 template <typename R>
 static qw_status action_impl(int n, const R *diag, const double *h, const double *J, double gamma, double t,
                              const void *psi_in, void *psi_out, double tol, int method, void *workspace,
@@ -652,6 +724,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
     const uint64_t N = uint64_t(1) << n;
+    EventTimer timer(info && info->timing, s);
+    timer.mark(0);
 
     EnergyTables T{};
     double c = 0.0, r = 0.0;
@@ -673,7 +747,9 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     const int eg = grid_for(nvec, 256 * 4, 1 << 16);
 
     if (info) {
+        const int want = info->timing;
         std::memset(info, 0, sizeof(*info));
+        info->timing = want;
         info->n = n;
         info->shift_c = c;
         info->radius_r = r;
@@ -682,10 +758,11 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     const C *psi = static_cast<const C *>(psi_in);
     C *out = static_cast<C *>(psi_out);
     if (r == 0.0) {
+        timer.mark(1);
         hipLaunchKernelGGL(k_scale<R>, dim3(eg), dim3(256), 0, s, reinterpret_cast<const V *>(psi),
                            reinterpret_cast<V *>(out), (R)ph_r, (R)ph_i, nvec);
         QW_HIP(hipGetLastError());
-        return QW_OK;
+        return timer.finish(info);
     }
 
     // normalised diagonal
@@ -745,25 +822,28 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         OnchipItem<R> *ditem = reinterpret_cast<OnchipItem<R> *>(ws + L.items);
         QW_HIP(hipMemcpyAsync(dcoef, ch.data(), ch.size() * sizeof(C), hipMemcpyHostToDevice, s));
         QW_HIP(hipMemcpyAsync(ditem, &item, sizeof(item), hipMemcpyHostToDevice, s));
+        timer.mark(1);
         hipLaunchKernelGGL((k_onchip<R, Cfg<R>::TB, ONCHIP_NT>), dim3(1), dim3(ONCHIP_NT), 0, s,
                            (const OnchipItem<R> *)ditem, (const int *)nullptr, 1);
         QW_HIP(hipGetLastError());
         QW_HIP(hipStreamSynchronize(s));  // host copies of ch/item go out of scope
-        return QW_OK;
+        return timer.finish(info);
     }
 
     if (K == 0) {
         double cr, ci;
         coef_of(0, cr, ci);
         const double pr = cr * ph_r - ci * ph_i, pi = cr * ph_i + ci * ph_r;
+        timer.mark(1);
         hipLaunchKernelGGL(k_scale<R>, dim3(eg), dim3(256), 0, s, reinterpret_cast<const V *>(psi),
                            reinterpret_cast<V *>(out), (R)pr, (R)pi, nvec);
         QW_HIP(hipGetLastError());
-        return QW_OK;
+        return timer.finish(info);
     }
 
     C *B1 = reinterpret_cast<C *>(ws + L.b1);
     C *B2 = reinterpret_cast<C *>(ws + L.b2);
+    timer.mark(1);
     {
         double cr, ci;
         coef_of(K, cr, ci);
@@ -781,6 +861,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     pa.g = (R)g;
     pa.n = n;
     const int P = (int)plan.size();
+    PassTimer ptimer(info && info->timing == 2, s, K * P + 1);
+    ptimer.mark();
     for (int k = K - 1; k >= 0; --k) {
         double cr, ci;
         coef_of(k, cr, ci);
@@ -800,11 +882,14 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
             pa.h = plan[p].h;
             const uint64_t ntiles = N >> (plan[p].L + plan[p].h);
             launch_pass<R>(pa, p == 0, otf, ntiles, s);
+            ptimer.mark();
         }
         QW_HIP(hipGetLastError());
         std::swap(B1, B2);
     }
-    return QW_OK;
+    qw_status tst = timer.finish(info);
+    if (tst != QW_OK) return tst;
+    return ptimer.finish(info, P);
 }
 
 template <typename R>
