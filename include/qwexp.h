@@ -129,6 +129,59 @@ qw_status qw_expm_action_c128(int n, const double *diag, const double *h, const 
                               double tol, qw_method method,
                               void *workspace, size_t ws_bytes, void *stream, qw_info *info);
 
+/* ---- batched form (section III.A: many instances per launch) ----------- */
+
+/* One instance of a batch.  Couplings h (n doubles) then J (n(n-1)/2 doubles,
+ * packed row-major upper triangle) start at off_hJ in the host coupling pool;
+ * the complex64 input and output states start at off_psi / off_out
+ * (counted in amplitudes, even) in the device state pools. */
+typedef struct {
+    int n;              /* qubits, 1..22                                         */
+    int reserved;
+    double gamma, t, tol;
+    int64_t off_hJ, off_psi, off_out;
+} qw_batch_item;
+
+typedef struct {
+    int timing;         /* in: nonzero times setup and recurrence with HIP events */
+    int count, small_count, large_count, max_K, launches, waves;
+    long long amp_terms;   /* sum over instances of 2^n K                         */
+    long long wave_bytes;  /* working-set cap per wave used (0: one wave)         */
+    float setup_ms, loop_ms;
+} qw_batch_info;
+
+/* Workspace bytes for qw_expm_action_batched_c64 (0 if the batch is invalid). */
+size_t qw_batched_workspace_bytes_c64(const qw_batch_item *items, int count, const double *hJ_pool);
+
+/* psi_out_i = exp(-i t_i (H_P,i + gamma_i sum_j X_j)) psi_in_i for every item,
+ * complex64, each instance with its own spectral shift, bound and coefficients
+ * (degree chosen for its own tol).  Instances with n <= 13 run in one
+ * persistent on-chip launch; larger ones in grouped two-pass launches captured
+ * into a HIP graph (eager launches when stream is NULL), in waves whose size is
+ * read from the tune file tune_cache (may be NULL: one wave).
+ *   items : host array of count items; hJ_pool: host doubles;
+ *   psi_pool / out_pool : device complex64 pools (16-byte aligned; output
+ *   ranges must not overlap each other or any input range);
+ *   workspace : device, >= qw_batched_workspace_bytes_c64 bytes, 256-aligned.
+ * Synchronises the stream (bound read-back, and at the end). */
+qw_status qw_expm_action_batched_c64(const qw_batch_item *items, int count, const double *hJ_pool,
+                                     const void *psi_pool, void *out_pool, qw_method method,
+                                     void *workspace, size_t ws_bytes, const char *tune_cache,
+                                     void *stream, qw_batch_info *info);
+
+/* Same with an explicit schedule: wave_bytes caps the working set of a wave
+ * (0 = all large instances in one wave); use_graph = 0 launches eagerly. */
+qw_status qw_expm_action_batched_c64_sched(const qw_batch_item *items, int count, const double *hJ_pool,
+                                           const void *psi_pool, void *out_pool, qw_method method,
+                                           void *workspace, size_t ws_bytes, long long wave_bytes,
+                                           int use_graph, void *stream, qw_batch_info *info);
+
+/* Autotuner: runs the batch with several wave sizes, keeps the fastest and
+ * appends "<size signature> <wave bytes> <ms>" to the text file tune_cache. */
+qw_status qw_batched_tune_c64(const qw_batch_item *items, int count, const double *hJ_pool,
+                              const void *psi_pool, void *out_pool, void *workspace, size_t ws_bytes,
+                              const char *tune_cache, void *stream, long long *best_wave_bytes);
+
 const char *qw_last_error(void);
 
 /* Host-only self check of the tile index maps used by the Clenshaw passes for

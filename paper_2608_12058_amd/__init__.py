@@ -228,3 +228,114 @@ def expm_action(psi, gamma: float, t: float, *, diag=None, h=None, J=None, tol: 
 def debug_check_plan(n: int, precision: int) -> int:
     """Host-only check of the pass index maps (number of passes, or < 0)."""
     return int(lib().qw_debug_check_plan(int(n), int(precision)))
+
+
+# ------------------------------------------------------------------ batched form
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("reserved", ctypes.c_int), ("gamma", ctypes.c_double),
+                ("t", ctypes.c_double), ("tol", ctypes.c_double), ("off_hJ", ctypes.c_int64),
+                ("off_psi", ctypes.c_int64), ("off_out", ctypes.c_int64)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("timing", ctypes.c_int), ("count", ctypes.c_int), ("small_count", ctypes.c_int),
+                ("large_count", ctypes.c_int), ("max_K", ctypes.c_int), ("launches", ctypes.c_int),
+                ("waves", ctypes.c_int), ("amp_terms", ctypes.c_longlong), ("wave_bytes", ctypes.c_longlong),
+                ("setup_ms", ctypes.c_float), ("loop_ms", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _declare_batched(lib):
+    if getattr(lib, "_qw_batched_declared", False):
+        return
+    lib.qw_batched_workspace_bytes_c64.restype = _sz
+    lib.qw_batched_workspace_bytes_c64.argtypes = [ctypes.POINTER(BatchItem), _i, _dp]
+    lib.qw_expm_action_batched_c64.argtypes = [ctypes.POINTER(BatchItem), _i, _dp, _vp, _vp, _i, _vp, _sz,
+                                               ctypes.c_char_p, _vp, ctypes.POINTER(BatchInfo)]
+    lib.qw_expm_action_batched_c64_sched.argtypes = [ctypes.POINTER(BatchItem), _i, _dp, _vp, _vp, _i, _vp, _sz,
+                                                     ctypes.c_longlong, _i, _vp, ctypes.POINTER(BatchInfo)]
+    lib.qw_batched_tune_c64.argtypes = [ctypes.POINTER(BatchItem), _i, _dp, _vp, _vp, _vp, _sz,
+                                        ctypes.c_char_p, _vp, ctypes.POINTER(ctypes.c_longlong)]
+    lib._qw_batched_declared = True
+
+
+class Batch:
+    """Independent complex64 instances packed for qw_expm_action_batched_c64.
+
+    instances: dicts with n, gamma, t, tol, h, J.  The input states live in one
+    device pool (``state(i)`` views), outputs in another (``output(i)``)."""
+
+    def __init__(self, instances, device="cuda"):
+        torch = _torch()
+        _declare_batched(lib())
+        self.count = len(instances)
+        self.items = (BatchItem * self.count)()
+        hj, off_hj, off = [], 0, 0
+        self.offsets = []
+        for i, ins in enumerate(instances):
+            n = int(ins["n"])
+            N = 1 << n
+            h = np.asarray(ins["h"], dtype=np.float64).reshape(n)
+            J = np.asarray(ins["J"], dtype=np.float64).reshape(n * (n - 1) // 2)
+            it = self.items[i]
+            it.n, it.gamma, it.t, it.tol = n, float(ins["gamma"]), float(ins["t"]), float(ins.get("tol", 1e-6))
+            it.off_hJ, it.off_psi, it.off_out = off_hj, off, off
+            hj += [h, J]
+            off_hj += n + J.size
+            self.offsets.append((off, N))
+            off += N + (N & 1)          # keep every state 16-byte aligned
+        self.hJ = np.ascontiguousarray(np.concatenate(hj)) if hj else np.zeros(0)
+        self.total = off
+        self.psi_pool = torch.zeros(max(off, 2), dtype=torch.complex64, device=device)
+        self.out_pool = torch.zeros_like(self.psi_pool)
+        self.ws_bytes = int(lib().qw_batched_workspace_bytes_c64(self.items, self.count, self.hJ.ctypes.data_as(_dp)))
+        if self.ws_bytes == 0:
+            raise QwError(QW_EINVAL, lib().qw_last_error().decode())
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+
+    def state(self, i):
+        o, N = self.offsets[i]
+        return self.psi_pool[o:o + N]
+
+    def output(self, i):
+        o, N = self.offsets[i]
+        return self.out_pool[o:o + N]
+
+    def ws_ptr(self) -> int:
+        return (self._ws.data_ptr() + 255) & ~255
+
+
+def expm_action_batched(batch: Batch, method: str = "cheb", tune_cache: str | None = None, stream=None,
+                        timing: int = 0, wave_bytes: int | None = None, use_graph: bool = True) -> dict:
+    """Run every instance of the batch; outputs land in batch.out_pool.  With
+    wave_bytes / use_graph given the schedule is explicit, otherwise it comes
+    from the tune file (or one wave)."""
+    L = lib()
+    _declare_batched(L)
+    info = BatchInfo()
+    info.timing = int(timing)
+    args = (batch.items, batch.count, batch.hJ.ctypes.data_as(_dp), _vp(batch.psi_pool.data_ptr()),
+            _vp(batch.out_pool.data_ptr()), _METHODS[method], _vp(batch.ws_ptr()), batch.ws_bytes)
+    if wave_bytes is None and use_graph:
+        st = L.qw_expm_action_batched_c64(*args, tune_cache.encode() if tune_cache else None, _stream_ptr(stream),
+                                          ctypes.byref(info))
+    else:
+        st = L.qw_expm_action_batched_c64_sched(*args, int(wave_bytes or 0), 1 if use_graph else 0,
+                                                _stream_ptr(stream), ctypes.byref(info))
+    _check(st)
+    return info.as_dict()
+
+
+def batched_tune(batch: Batch, tune_cache: str, stream=None) -> int:
+    """Time the candidate wave sizes on this batch and append the best to tune_cache."""
+    L = lib()
+    _declare_batched(L)
+    best = ctypes.c_longlong(0)
+    _check(L.qw_batched_tune_c64(batch.items, batch.count, batch.hJ.ctypes.data_as(_dp),
+                                 _vp(batch.psi_pool.data_ptr()), _vp(batch.out_pool.data_ptr()),
+                                 _vp(batch.ws_ptr()), batch.ws_bytes, tune_cache.encode(), _stream_ptr(stream),
+                                 ctypes.byref(best)))
+    return int(best.value)

@@ -17,9 +17,7 @@
 // tile spanning a group of high bits (plus contiguous "passenger" bits for
 // coalescing) and adds that group's flips.  Small instances (n <= 13) run the
 // whole recurrence inside one workgroup with the vector resident in LDS.
-#include "qw_device.h"
-#include "qw_internal.h"
-#include "qwexp.h"
+#include "qw_kernels.h"
 
 #include <hip/hip_runtime.h>
 
@@ -35,23 +33,6 @@ static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 
 // ---------------------------------------------------------------------------
-// Compile-time configuration
-// ---------------------------------------------------------------------------
-template <typename R> struct Cfg;
-template <> struct Cfg<float> {
-    static constexpr int TB = 13;     // tile bits of a pass (2^13 x 8 B = 64 KB LDS)
-    static constexpr int NT = 512;    // threads per pass workgroup
-    static constexpr int LMIN = 4;    // passenger bits: rows of >= 128 B
-};
-template <> struct Cfg<double> {
-    static constexpr int TB = 12;     // 2^12 x 16 B = 64 KB LDS
-    static constexpr int NT = 512;
-    static constexpr int LMIN = 3;
-};
-static constexpr int ONCHIP_NT = 1024;
-static constexpr int MAXPART = 4096;          // reduction partials
-static constexpr int KMAX_ONCHIP = 1 << 17;   // coefficient slots for on-chip runs
-static constexpr int LB_TAB = 13;             // low bits of the energy tables
 
 // ---------------------------------------------------------------------------
 // Kernels: energies, spectral bound, normalisation
@@ -190,268 +171,9 @@ __global__ void k_qtilde(const double *Q, int LB, double inv_r, float *Qt)
 }
 
 // ---------------------------------------------------------------------------
-// Kernels: Clenshaw recurrence
-// ---------------------------------------------------------------------------
-
-// b1 = c_K psi, b2 = 0   (Eq. recursion: b_K = c_K v, b_{K+1} = 0)
-template <typename R>
-__global__ void __launch_bounds__(256) k_init(const CVec<R> *psi, CVec<R> *b1, CVec<R> *b2,
-                                              R cr, R ci, uint64_t nvec)
-{
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nvec;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const CVec<R> p = psi[i];
-        CVec<R> o, z;
-#pragma unroll
-        for (int v = 0; v < CVec<R>::N; ++v) {
-            o.v[v].x = cr * p.v[v].x - ci * p.v[v].y;
-            o.v[v].y = cr * p.v[v].y + ci * p.v[v].x;
-            z.v[v].x = R(0);
-            z.v[v].y = R(0);
-        }
-        b1[i] = o;
-        b2[i] = z;
-    }
-}
-
-// out = (cr + i ci) psi   (K = 0 or a zero spectral bound)
-template <typename R>
-__global__ void __launch_bounds__(256) k_scale(const CVec<R> *psi, CVec<R> *out, R cr, R ci, uint64_t nvec)
-{
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nvec;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const CVec<R> p = psi[i];
-        CVec<R> o;
-#pragma unroll
-        for (int v = 0; v < CVec<R>::N; ++v) {
-            o.v[v].x = cr * p.v[v].x - ci * p.v[v].y;
-            o.v[v].y = cr * p.v[v].y + ci * p.v[v].x;
-        }
-        out[i] = o;
-    }
-}
-
-template <typename R> struct PassArgs {
-    using C = typename Cplx<R>::T;
-    const C *b1;   // b_{k+1}: its flips over the tile's group are summed
-    const C *acc;  // START: b_{k+2};  ADD: the partial b_k
-    C *dst;        // output, may alias acc
-    const C *psi;  // START: v
-    const R *d;    // START: normalised diagonal (unless on the fly)
-    const float *Qt;   // on the fly: Q / r table over the low 13 bits
-    const double *hJ;  // on the fly: h then J (device)
-    double otf_c, otf_inv_r;
-    R g;           // gamma / r
-    R scale;       // 2 inside the recurrence, 1 for the final step
-    R cr, ci;      // START: c_k
-    R pr, pi;      // multiplier of the result (the global phase on the last pass)
-    int n, L, g0, h;
-};
-
-// One pass of one Clenshaw term over one tile (see tile_base/tile_index).
-//  START: dst = scale * (d .* b1 + g * F_group b1) - acc + c_k psi
-//  ADD:   dst = acc + scale * g * F_group b1
-// then dst *= (pr + i pi).  F_group sums the flips of the tile's h group bits.
-template <typename R, int TB, int NT, bool START, bool OTF>
-__global__ void __launch_bounds__(NT) k_pass(PassArgs<R> a)
-{
-    using C = typename Cplx<R>::T;
-    using V = CVec<R>;
-    constexpr int VE = V::N;
-    constexpr int PER = (1 << TB) / (NT * VE);
-    static_assert(PER >= 1, "tile smaller than one vector per thread");
-    __shared__ C lds[1 << TB];
-    __shared__ float fld[OTF ? LB_TAB : 1];
-    __shared__ float fbase;
-
-    const uint32_t TE = 1u << (a.L + a.h);
-    const uint64_t base = tile_base(blockIdx.x, a.L, a.g0, a.h);
-
-    if constexpr (OTF) {
-        // Per-tile fields of the diagonal: the tile is the contiguous block of
-        // the low 13 bits, so its high bits are fixed (blockIdx.x).
-        __shared__ double f64[LB_TAB];
-        __shared__ double c64;
-        EnergyTables T{a.hJ, a.hJ + a.n, nullptr, a.n, LB_TAB};
-        tile_fields(T, (uint64_t)blockIdx.x, f64, &c64);
-        __syncthreads();
-        if (threadIdx.x < LB_TAB) fld[threadIdx.x] = (float)(f64[threadIdx.x] * a.otf_inv_r);
-        if (threadIdx.x == 0) fbase = (float)((c64 - a.otf_c) * a.otf_inv_r);
-    }
-
-    V own[PER], accv[PER];
-    V psiv[START ? PER : 1];
-    R dv[START ? PER : 1][VE];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
-        if (e < TE) {
-            const uint64_t idx = tile_index(base, e, a.L, a.g0);
-            own[q] = *reinterpret_cast<const V *>(a.b1 + idx);
-            accv[q] = *reinterpret_cast<const V *>(a.acc + idx);
-            if constexpr (START) {
-                psiv[q] = *reinterpret_cast<const V *>(a.psi + idx);
-                if constexpr (!OTF) {
-#pragma unroll
-                    for (int v = 0; v < VE; ++v) dv[q][v] = a.d[idx + v];
-                }
-            }
-#pragma unroll
-            for (int v = 0; v < VE; ++v) lds[e + v] = own[q].v[v];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
-        if (e < TE) {
-            const uint64_t idx = tile_index(base, e, a.L, a.g0);
-            V out;
-#pragma unroll
-            for (int v = 0; v < VE; ++v) {
-                const uint32_t ee = e + v;
-                R sr = R(0), si = R(0);
-                for (int j = 0; j < a.h; ++j) {
-                    const C nb = lds[ee ^ (1u << (a.L + j))];
-                    sr += nb.x;
-                    si += nb.y;
-                }
-                C o;
-                if constexpr (START) {
-                    R dd;
-                    if constexpr (OTF) {
-                        float s = fbase + a.Qt[ee];
-#pragma unroll
-                        for (int j = 0; j < LB_TAB; ++j) s += ((ee >> j) & 1) ? -fld[j] : fld[j];
-                        dd = (R)s;
-                    } else {
-                        dd = dv[q][v];
-                    }
-                    const C b = own[q].v[v], ac = accv[q].v[v], ps = psiv[q].v[v];
-                    const R hr = dd * b.x + a.g * sr;
-                    const R hi = dd * b.y + a.g * si;
-                    o.x = (a.scale * hr - ac.x) + (a.cr * ps.x - a.ci * ps.y);
-                    o.y = (a.scale * hi - ac.y) + (a.cr * ps.y + a.ci * ps.x);
-                } else {
-                    const C ac = accv[q].v[v];
-                    const R sg = a.scale * a.g;
-                    o.x = ac.x + sg * sr;
-                    o.y = ac.y + sg * si;
-                }
-                out.v[v].x = a.pr * o.x - a.pi * o.y;
-                out.v[v].y = a.pr * o.y + a.pi * o.x;
-            }
-            *reinterpret_cast<V *>(a.dst + idx) = out;
-        }
-    }
-}
-
-// Whole recurrence of one small instance (n <= TB) inside one workgroup.
-template <typename R> struct OnchipItem {
-    using C = typename Cplx<R>::T;
-    const C *psi;
-    C *out;
-    const R *d;
-    const C *coef;  // c_0..c_K
-    R g;
-    R pr, pi;       // global phase
-    int n, K;
-};
-
-template <typename R, int TB, int NT>
-__global__ void __launch_bounds__(NT) k_onchip(const OnchipItem<R> *items, const int *order, int count)
-{
-    using C = typename Cplx<R>::T;
-    constexpr int PER = (1 << TB) / NT;
-    static_assert(PER >= 1, "");
-    __shared__ C lds[1 << TB];
-    for (int it = blockIdx.x; it < count; it += gridDim.x) {
-        const OnchipItem<R> I = items[order ? order[it] : it];
-        const uint32_t N = 1u << I.n;
-        C ps[PER], b1[PER], b2[PER];
-        R dd[PER];
-        const C cK = I.coef[I.K];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const uint32_t e = q * NT + threadIdx.x;
-            if (e < N) {
-                ps[q] = I.psi[e];
-                dd[q] = I.d[e];
-                b1[q].x = cK.x * ps[q].x - cK.y * ps[q].y;
-                b1[q].y = cK.x * ps[q].y + cK.y * ps[q].x;
-                b2[q].x = R(0);
-                b2[q].y = R(0);
-                lds[e] = b1[q];
-            }
-        }
-        __syncthreads();
-        for (int k = I.K - 1; k >= 1; --k) {
-            const C ck = I.coef[k];
-            C nb[PER];
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const uint32_t e = q * NT + threadIdx.x;
-                if (e < N) {
-                    R sr = R(0), si = R(0);
-                    for (int j = 0; j < I.n; ++j) {
-                        const C x = lds[e ^ (1u << j)];
-                        sr += x.x;
-                        si += x.y;
-                    }
-                    const R hr = dd[q] * b1[q].x + I.g * sr;
-                    const R hi = dd[q] * b1[q].y + I.g * si;
-                    nb[q].x = (R(2) * hr - b2[q].x) + (ck.x * ps[q].x - ck.y * ps[q].y);
-                    nb[q].y = (R(2) * hi - b2[q].y) + (ck.x * ps[q].y + ck.y * ps[q].x);
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const uint32_t e = q * NT + threadIdx.x;
-                if (e < N) {
-                    b2[q] = b1[q];
-                    b1[q] = nb[q];
-                    lds[e] = nb[q];
-                }
-            }
-            __syncthreads();
-        }
-        const C c0 = I.coef[0];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const uint32_t e = q * NT + threadIdx.x;
-            if (e < N) {
-                C y;
-                if (I.K == 0) {
-                    y.x = c0.x * ps[q].x - c0.y * ps[q].y;
-                    y.y = c0.x * ps[q].y + c0.y * ps[q].x;
-                } else {
-                    R sr = R(0), si = R(0);
-                    for (int j = 0; j < I.n; ++j) {
-                        const C x = lds[e ^ (1u << j)];
-                        sr += x.x;
-                        si += x.y;
-                    }
-                    const R hr = dd[q] * b1[q].x + I.g * sr;
-                    const R hi = dd[q] * b1[q].y + I.g * si;
-                    y.x = (hr - b2[q].x) + (c0.x * ps[q].x - c0.y * ps[q].y);
-                    y.y = (hi - b2[q].y) + (c0.x * ps[q].y + c0.y * ps[q].x);
-                }
-                C o;
-                o.x = I.pr * y.x - I.pi * y.y;
-                o.y = I.pr * y.y + I.pi * y.x;
-                I.out[e] = o;
-            }
-        }
-        __syncthreads();  // lds is reused by the next instance
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 
-static inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct WsLayout {
     size_t b1, b2, d, part, red, hj, q, qt, coef, items, total;
@@ -478,47 +200,6 @@ static WsLayout ws_layout(int n, int prec, bool otf)
     return L;
 }
 
-struct PassPlan { int L, g0, h; };
-
-template <typename R>
-static std::vector<PassPlan> plan_passes(int n)
-{
-    constexpr int TB = Cfg<R>::TB, LMIN = Cfg<R>::LMIN;
-    std::vector<PassPlan> P;
-    const int h0 = std::min(n, TB);
-    P.push_back({0, 0, h0});
-    const int rem = n - h0;
-    if (rem > 0) {
-        const int cap = TB - LMIN;
-        const int np = (rem + cap - 1) / cap;
-        int g = h0;
-        for (int p = 0; p < np; ++p) {
-            const int hh = rem / np + (p < rem % np ? 1 : 0);
-            P.push_back({TB - hh, g, hh});
-            g += hh;
-        }
-    }
-    return P;
-}
-
-#define QW_HIP(call)                                                                   \
-    do {                                                                               \
-        hipError_t e_ = (call);                                                        \
-        if (e_ != hipSuccess) {                                                        \
-            set_error(std::string(#call) + ": " + hipGetErrorString(e_));              \
-            return QW_EHIP;                                                            \
-        }                                                                              \
-    } while (0)
-
-static inline int grid_for(uint64_t work, int per_block, int cap)
-{
-    uint64_t g = (work + per_block - 1) / per_block;
-    if (g < 1) g = 1;
-    if (g > (uint64_t)cap) g = cap;
-    return (int)g;
-}
-
-template <typename R> static constexpr int prec_of() { return sizeof(R) == 4 ? 64 : 128; }
 
 // Upload h, J, build the Q table; returns the tables view.
 static qw_status setup_tables(int n, const double *h, const double *J, char *ws, const WsLayout &L,
@@ -569,7 +250,6 @@ static qw_status minmax(int n, const R *diag, const EnergyTables *T, char *ws, c
     return QW_OK;
 }
 
-static bool finite(double x) { return std::isfinite(x); }
 
 template <typename R>
 static qw_status validate(int n, const R *diag, const double *h, const double *J, double gamma, double t,
@@ -790,15 +470,6 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         set_error("coefficient setup failed");
         return QW_ENOCONV;
     }
-    auto coef_of = [&](int k, double &cr, double &ci) {
-        const double al = alpha[k];
-        switch (k & 3) {
-        case 0: cr = al; ci = 0.0; break;
-        case 1: cr = 0.0; ci = -al; break;
-        case 2: cr = -al; ci = 0.0; break;
-        default: cr = 0.0; ci = al; break;
-        }
-    };
     const std::vector<PassPlan> plan = plan_passes<R>(n);
     if (info) {
         info->K = K;
@@ -813,7 +484,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         std::vector<C> ch(K + 1);
         for (int k = 0; k <= K; ++k) {
             double cr, ci;
-            coef_of(k, cr, ci);
+            coef_of(alpha, k, cr, ci);
             ch[k].x = (R)cr;
             ch[k].y = (R)ci;
         }
@@ -832,7 +503,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
 
     if (K == 0) {
         double cr, ci;
-        coef_of(0, cr, ci);
+        coef_of(alpha, 0, cr, ci);
         const double pr = cr * ph_r - ci * ph_i, pi = cr * ph_i + ci * ph_r;
         timer.mark(1);
         hipLaunchKernelGGL(k_scale<R>, dim3(eg), dim3(256), 0, s, reinterpret_cast<const V *>(psi),
@@ -846,7 +517,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     timer.mark(1);
     {
         double cr, ci;
-        coef_of(K, cr, ci);
+        coef_of(alpha, K, cr, ci);
         hipLaunchKernelGGL(k_init<R>, dim3(eg), dim3(256), 0, s, reinterpret_cast<const V *>(psi),
                            reinterpret_cast<V *>(B1), reinterpret_cast<V *>(B2), (R)cr, (R)ci, nvec);
         QW_HIP(hipGetLastError());
@@ -865,7 +536,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     ptimer.mark();
     for (int k = K - 1; k >= 0; --k) {
         double cr, ci;
-        coef_of(k, cr, ci);
+        coef_of(alpha, k, cr, ci);
         const bool fin = (k == 0);
         for (int p = 0; p < P; ++p) {
             pa.b1 = B1;
