@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c128", action="store_true")
     ap.add_argument("--cpu-terms", type=int, default=30, help="Clenshaw terms of the CPU oracle sample")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--n32", action="store_true", help="also time the 32-qubit on-the-fly workload (~1 min)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM counters)")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic_n28_c64.json"),
@@ -70,6 +73,88 @@ def cpu_baseline(n, h, J, gamma, t, tol, terms):
     return {"value": (1 << n) * terms / sec, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{terms} Clenshaw terms of the same {n}-qubit instance, complex128 plain C loops "
                       f"({sec:.1f} s)"}
+
+
+def batched_leg(torch, qw, synth, np):
+    """256 instances (n ~ U{12..22}, t ~ U(0.1, 20), gamma ~ U(0.2, 2), |+>,
+    complex64, tol 1e-6) in one batched call, against the same instances run
+    one by one in complex128 (tol 1e-6) and in complex64."""
+    insts = synth.batch_instances(256, 0)
+    for ins in insts:
+        ins["tol"] = 1e-6
+    b = qw.Batch(insts)
+    for i, ins in enumerate(insts):
+        b.state(i).fill_(1.0 / np.sqrt(1 << ins["n"]))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        qw.expm_action_batched(b, stream=stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        info = qw.expm_action_batched(b, stream=stream, timing=1)
+        stream.synchronize()
+        wall = time.perf_counter() - t0
+    out = {"instances": 256, "amp_terms": info["amp_terms"], "ms": wall * 1e3, "loop_ms": info["loop_ms"],
+           "setup_ms": info["setup_ms"], "value": info["amp_terms"] / wall, "unit": UNIT,
+           "launches": info["launches"], "waves": info["waves"], "small": info["small_count"]}
+    for prec, dt in ((128, torch.complex128), (64, torch.complex64)):
+        t0 = time.perf_counter()
+        for i, ins in enumerate(insts):
+            x = b.state(i).to(dt)
+            qw.expm_action(x, ins["gamma"], ins["t"], h=ins["h"], J=ins["J"], tol=1e-6)
+        torch.cuda.synchronize()
+        out[f"one_by_one_c{prec}_ms"] = (time.perf_counter() - t0) * 1e3
+    out["speedup_vs_c128_one_by_one"] = out["one_by_one_c128_ms"] / out["ms"]
+    out["speedup_vs_c64_one_by_one"] = out["one_by_one_c64_ms"] / out["ms"]
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
+def grad_leg(torch, qw, synth, np):
+    """Energy and gradient of the 20-qubit, 16-segment anneal (complex64 forward,
+    single-precision adjoint) against the plain complex128 forward anneal."""
+    n = 20
+    h, J = synth.sk_instance(n, 0)
+    gam, ts = synth.anneal_schedule(16)
+    x = synth.plus_state_torch(n, "cuda", torch.complex64)
+    qw.anneal_energy_grad(h, J, gam, ts, x, ckpt_every=8)
+    t0 = time.perf_counter()
+    E, g, info = qw.anneal_energy_grad(h, J, gam, ts, x, ckpt_every=8, timing=1)
+    wall = time.perf_counter() - t0
+    y = x.to(torch.complex128)
+    for gg, tt in zip(gam, ts):
+        y, _ = qw.expm_action(y, float(gg), float(tt), h=h, J=J, tol=1e-12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y = x.to(torch.complex128)
+    K128 = 0
+    for gg, tt in zip(gam, ts):
+        y, i128 = qw.expm_action(y, float(gg), float(tt), h=h, J=J, tol=1e-12)
+        K128 += i128["K"]
+    torch.cuda.synchronize()
+    wall128 = time.perf_counter() - t0
+    return {"n": n, "segments": 16, "E": E, "sum_K": info["sum_K"], "ms_grad": wall * 1e3,
+            "ms_c128_forward": wall128 * 1e3, "sum_K_c128": K128, "ratio_grad_vs_c128_forward": wall / wall128,
+            "params": 16 + 16 + n + n * (n - 1) // 2}
+
+
+def n32_leg(torch, qw, synth):
+    """32 qubits, complex64, SK seed 0, gamma = 1, t = 5, tol 2^-23, |+>, diagonal
+    recomputed in every term from per-tile tables (4 resident vectors, 137 GB)."""
+    n = 32
+    h, J = synth.sk_instance(n, 0)
+    psi = synth.plus_state_torch(n, "cuda", torch.complex64)
+    t0 = time.perf_counter()
+    y, info = qw.expm_action(psi, 1.0, 5.0, h=h, J=J, tol=2.0 ** -23, out=psi, timing=1)
+    wall = time.perf_counter() - t0
+    N = 1 << n
+    out = {"n": n, "K": info["K"], "passes": info["passes"], "ms": wall * 1e3, "loop_ms": info["loop_ms"],
+           "value": N * info["K"] / wall, "unit": UNIT,
+           "hbm_GBps_alg": (24 + 32 * info["K"]) * N / (info["loop_ms"] * 1e-3) / 1e9,
+           "norm": torch.linalg.vector_norm(y.to(torch.complex128)).item()}
+    del y, psi
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -173,6 +258,16 @@ def main():
         result["c64_vs_c128_time_ratio"] = (tb - ta) * 1e3 / ms_step
         del ws128, psi128, out128
         torch.cuda.empty_cache()
+
+    if not args.no_batched:
+        log("[bench] batched: 256 SK instances, n ~ U{12..22}")
+        result["batched"] = batched_leg(torch, qw, synth, np)
+    if not args.no_grad:
+        log("[bench] gradient: n=20, 16 segments")
+        result["grad"] = grad_leg(torch, qw, synth, np)
+    if args.n32:
+        log("[bench] n=32 on-the-fly diagonal")
+        result["n32"] = n32_leg(torch, qw, synth)
 
     if args.calib_copy:
         log("[bench] calibration copy (2 GiB)")

@@ -63,6 +63,11 @@ typedef struct {
     float setup_ms;     /* out (timing): bound, diagonal, coefficients            */
     float loop_ms;      /* out (timing): all Clenshaw terms and the final step    */
     float pass_ms[4];   /* out (timing 2): pass p summed over all terms           */
+    int monitor;        /* in: nonzero measures ||b_k|| of every term (fused in the
+                           last pass), fills eval_bound and checks the growth      */
+    double growth;      /* out (monitor): max over k of ||b_k|| / its limit for a
+                           valid bound (> 1 means QW_EDIVERGE)                     */
+    double out_norm;    /* out (monitor): ||psi_out||                             */
 } qw_info;
 
 /* Chebyshev coefficients of exp(-i a x) on [-1, 1] (section II.B.1, Eq. cheb,
@@ -181,6 +186,57 @@ qw_status qw_expm_action_batched_c64_sched(const qw_batch_item *items, int count
 qw_status qw_batched_tune_c64(const qw_batch_item *items, int count, const double *hJ_pool,
                               const void *psi_pool, void *out_pool, void *workspace, size_t ws_bytes,
                               const char *tune_cache, void *stream, long long *best_wave_bytes);
+
+/* ---- anneal energy and gradient ----------------------------------------- */
+
+typedef struct {
+    int timing;            /* in: nonzero times the whole call with HIP events     */
+    int passes;            /* global passes per Clenshaw / adjoint term            */
+    int sum_K;             /* total degree over the segments                       */
+    long long amp_terms;   /* sum_s 2^n K_s of the forward sweep                   */
+    float total_ms;
+} qw_grad_info;
+
+/* Workspace bytes for qw_anneal_energy_grad_c64 (0 for invalid arguments).  The
+ * size is fixed from a host bound on every segment's degree. */
+size_t qw_anneal_workspace_bytes_c64(int n, const double *h, const double *J, int S, const double *gamma,
+                                     const double *t, int ckpt_every);
+
+/* Piecewise-constant anneal psi_s = exp(-i t_s (H_P + gamma_s sum_j X_j)) psi_{s-1},
+ * s = 1..S, evaluated with Chebyshev coefficients (complex64), its energy
+ * E = <psi_S|H_P|psi_S> and the gradient of E with respect to every gamma_s,
+ * t_s, h_j and J_jk by the adjoint of the Clenshaw recurrence (single-precision
+ * adjoint, double-precision reductions).  The spectral shift c, the bounds r_s
+ * and the degrees K_s are held fixed (stop-gradient); they are piecewise
+ * constant in the parameters.
+ *   h, J       : host couplings (SK layout as above); gamma, t: host, S values.
+ *   psi0       : device complex64 initial state (2^n amplitudes).
+ *   ckpt_every : window of the b_k recomputation; b_k pairs are checkpointed
+ *                every ckpt_every terms during the forward sweep (<= 0: one
+ *                window per segment, no checkpoints).
+ *   E, dgamma (S), dt (S), dh (n), dJ (n(n-1)/2): host outputs.
+ *   psiT_out   : device complex64, receives psi_S (may be NULL).
+ * 1 <= n <= 28.  Synchronises the stream once per segment. */
+qw_status qw_anneal_energy_grad_c64(int n, const double *h, const double *J, int S, const double *gamma,
+                                    const double *t, const void *psi0, double tol, int ckpt_every,
+                                    double *E, double *dgamma, double *dt, double *dh, double *dJ,
+                                    void *workspace, size_t ws_bytes, void *stream, void *psiT_out,
+                                    qw_grad_info *info);
+
+/* Same as qw_expm_action_c64 / _c128 with the spectral shift c and bound r given
+ * by the caller (no bound read-back).  r must bound the spectral radius of
+ * H - cI: the call always monitors ||b_k|| (as info->monitor does, fused into
+ * the last pass of each term), fills info->eval_bound, and returns QW_EDIVERGE
+ * when a Clenshaw vector or the result exceeds the limit that holds for any
+ * valid bound (section II.B.3 and |U_j| <= j + 1).  Synchronises at the end. */
+qw_status qw_expm_action_c64_bounded(int n, const float *diag, const double *h, const double *J, double gamma,
+                                     double t, double c, double r, const void *psi_in, void *psi_out,
+                                     double tol, qw_method method, void *workspace, size_t ws_bytes,
+                                     void *stream, qw_info *info);
+qw_status qw_expm_action_c128_bounded(int n, const double *diag, const double *h, const double *J,
+                                      double gamma, double t, double c, double r, const void *psi_in,
+                                      void *psi_out, double tol, qw_method method, void *workspace,
+                                      size_t ws_bytes, void *stream, qw_info *info);
 
 const char *qw_last_error(void);
 

@@ -35,7 +35,8 @@ class QwInfo(ctypes.Structure):
                 ("shift_c", ctypes.c_double), ("radius_r", ctypes.c_double), ("a", ctypes.c_double),
                 ("trunc_bound", ctypes.c_double), ("eval_bound", ctypes.c_double),
                 ("timing", ctypes.c_int), ("setup_ms", ctypes.c_float), ("loop_ms", ctypes.c_float),
-                ("pass_ms", ctypes.c_float * 4)]
+                ("pass_ms", ctypes.c_float * 4), ("monitor", ctypes.c_int), ("growth", ctypes.c_double),
+                ("out_norm", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -64,6 +65,9 @@ def _declare(lib):
     for name in ("qw_expm_action_c64", "qw_expm_action_c128"):
         f = getattr(lib, name)
         f.argtypes = [_i, _vp, _dp, _dp, _d, _d, _vp, _vp, _d, _i, _vp, _sz, _vp, ctypes.POINTER(QwInfo)]
+    for name in ("qw_expm_action_c64_bounded", "qw_expm_action_c128_bounded"):
+        f = getattr(lib, name)
+        f.argtypes = [_i, _vp, _dp, _dp, _d, _d, _d, _d, _vp, _vp, _d, _i, _vp, _sz, _vp, ctypes.POINTER(QwInfo)]
     lib.qw_debug_check_plan.argtypes = [_i, _i]
     lib.qw_debug_check_plan.restype = _i
     return lib
@@ -182,7 +186,7 @@ def spectral_bound(n: int, gamma: float, diag=None, h=None, J=None, precision: i
 
 def expm_action(psi, gamma: float, t: float, *, diag=None, h=None, J=None, tol: float = 2.0 ** -23,
                 method: str = "cheb", out=None, workspace: Workspace | None = None, stream=None,
-                timing: int = 0):
+                timing: int = 0, monitor: bool = False, bound: tuple | None = None):
     """psi(t) = exp(-i t (diag(E) + gamma sum_j X_j)) psi on the GPU.
 
     psi: contiguous complex64 or complex128 CUDA tensor of length 2^n.
@@ -190,7 +194,11 @@ def expm_action(psi, gamma: float, t: float, *, diag=None, h=None, J=None, tol: 
     complex128) or None with h (n values) and J (n(n-1)/2 values, packed upper
     triangle) given as host arrays.  timing=1 records HIP events around the
     setup and the Clenshaw loop (info["setup_ms"], info["loop_ms"]) and makes the
-    call synchronous; timing=2 also times every pass (info["pass_ms"]).  Returns (psi_out, info dict)."""
+    call synchronous; timing=2 also times every pass (info["pass_ms"]).
+    monitor=True measures every ||b_k|| and fills info["eval_bound"] (the
+    evaluation-error bound of section II.B.3).  bound=(c, r) skips the spectral
+    bound read-back and uses the caller's shift and radius, with the monitor on;
+    a radius too small to bound the spectrum raises QwError(QW_EDIVERGE).  Returns (psi_out, info dict)."""
     torch = _torch()
     if not (psi.is_cuda and psi.is_contiguous() and psi.dim() == 1):
         raise ValueError("psi must be a contiguous 1-D CUDA tensor")
@@ -218,10 +226,18 @@ def expm_action(psi, gamma: float, t: float, *, diag=None, h=None, J=None, tol: 
         workspace = Workspace.for_problem(n, prec, otf, device=psi.device)
     info = QwInfo()
     info.timing = int(timing)
-    fn = lib().qw_expm_action_c64 if prec == 64 else lib().qw_expm_action_c128
-    _check(fn(int(n), _vp(diag.data_ptr()) if diag is not None else None, hp, Jp, float(gamma), float(t),
-              _vp(psi.data_ptr()), _vp(out.data_ptr()), float(tol), _METHODS[method],
-              _vp(workspace.ptr()), workspace.nbytes, _stream_ptr(stream), ctypes.byref(info)))
+    info.monitor = 1 if monitor else 0
+    dptr = _vp(diag.data_ptr()) if diag is not None else None
+    if bound is None:
+        fn = lib().qw_expm_action_c64 if prec == 64 else lib().qw_expm_action_c128
+        _check(fn(int(n), dptr, hp, Jp, float(gamma), float(t), _vp(psi.data_ptr()), _vp(out.data_ptr()),
+                  float(tol), _METHODS[method], _vp(workspace.ptr()), workspace.nbytes, _stream_ptr(stream),
+                  ctypes.byref(info)))
+    else:
+        fn = lib().qw_expm_action_c64_bounded if prec == 64 else lib().qw_expm_action_c128_bounded
+        _check(fn(int(n), dptr, hp, Jp, float(gamma), float(t), float(bound[0]), float(bound[1]),
+                  _vp(psi.data_ptr()), _vp(out.data_ptr()), float(tol), _METHODS[method], _vp(workspace.ptr()),
+                  workspace.nbytes, _stream_ptr(stream), ctypes.byref(info)))
     return out, info.as_dict()
 
 
@@ -339,3 +355,94 @@ def batched_tune(batch: Batch, tune_cache: str, stream=None) -> int:
                                  _vp(batch.ws_ptr()), batch.ws_bytes, tune_cache.encode(), _stream_ptr(stream),
                                  ctypes.byref(best)))
     return int(best.value)
+
+
+# ------------------------------------------------------------------ anneal gradient
+
+class GradInfo(ctypes.Structure):
+    _fields_ = [("timing", ctypes.c_int), ("passes", ctypes.c_int), ("sum_K", ctypes.c_int),
+                ("amp_terms", ctypes.c_longlong), ("total_ms", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _declare_grad(lib):
+    if getattr(lib, "_qw_grad_declared", False):
+        return
+    lib.qw_anneal_workspace_bytes_c64.restype = _sz
+    lib.qw_anneal_workspace_bytes_c64.argtypes = [_i, _dp, _dp, _i, _dp, _dp, _i]
+    lib.qw_anneal_energy_grad_c64.argtypes = [_i, _dp, _dp, _i, _dp, _dp, _vp, _d, _i, _dp, _dp, _dp, _dp, _dp,
+                                              _vp, _sz, _vp, _vp, ctypes.POINTER(GradInfo)]
+    lib._qw_grad_declared = True
+
+
+def anneal_energy_grad(h, J, gammas, ts, psi0, tol: float = 2.0 ** -23, ckpt_every: int = 0, stream=None,
+                       timing: int = 0, psiT_out=None):
+    """E = <psi_S|H_P|psi_S> after the piecewise-constant anneal (gammas, ts) from
+    psi0 (complex64 CUDA tensor), and dE/d(gamma, t, h, J).  Returns
+    (E, {"gamma", "t", "h", "J"}, info)."""
+    torch = _torch()
+    L = lib()
+    _declare_grad(L)
+    if psi0.dtype != torch.complex64 or not psi0.is_cuda or not psi0.is_contiguous():
+        raise ValueError("psi0 must be a contiguous complex64 CUDA tensor")
+    n = psi0.numel().bit_length() - 1
+    S = len(gammas)
+    h_, hp = _host_f64(h, n)
+    J_, Jp = _host_f64(J, n * (n - 1) // 2)
+    g_, gp = _host_f64(gammas, S)
+    t_, tp = _host_f64(ts, S)
+    nb = int(L.qw_anneal_workspace_bytes_c64(n, hp, Jp, S, gp, tp, int(ckpt_every)))
+    if nb == 0:
+        raise QwError(QW_EINVAL, L.qw_last_error().decode())
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=psi0.device)
+    wsp = (ws.data_ptr() + 255) & ~255
+    E = ctypes.c_double(0.0)
+    dg, dt = np.zeros(S), np.zeros(S)
+    dh, dJ = np.zeros(n), np.zeros(max(n * (n - 1) // 2, 1))
+    info = GradInfo()
+    info.timing = int(timing)
+    _check(L.qw_anneal_energy_grad_c64(n, hp, Jp, S, gp, tp, _vp(psi0.data_ptr()), float(tol), int(ckpt_every),
+                                       ctypes.byref(E), dg.ctypes.data_as(_dp), dt.ctypes.data_as(_dp),
+                                       dh.ctypes.data_as(_dp), dJ.ctypes.data_as(_dp), _vp(wsp), nb,
+                                       _stream_ptr(stream), _vp(psiT_out.data_ptr()) if psiT_out is not None else None,
+                                       ctypes.byref(info)))
+    return E.value, {"gamma": dg, "t": dt, "h": dh, "J": dJ[:n * (n - 1) // 2]}, info.as_dict()
+
+
+def _make_anneal_function():
+    torch = _torch()
+
+    class AnnealEnergy(torch.autograd.Function):
+        """E(gamma, t, h, J) = <psi_S|H_P|psi_S> with the gradient from the
+        library's adjoint Clenshaw sweep (one library call computes both)."""
+
+        @staticmethod
+        def forward(ctx, gammas, ts, h, J, psi0, tol=2.0 ** -23, ckpt_every=0):
+            E, g, _ = anneal_energy_grad(h.detach().cpu().numpy(), J.detach().cpu().numpy(),
+                                         gammas.detach().cpu().numpy(), ts.detach().cpu().numpy(), psi0,
+                                         tol=tol, ckpt_every=ckpt_every)
+            grads = [torch.as_tensor(g[k], dtype=x.dtype, device=x.device)
+                     for k, x in (("gamma", gammas), ("t", ts), ("h", h), ("J", J))]
+            ctx.save_for_backward(*grads)
+            return torch.tensor(E, dtype=torch.float64, device=gammas.device)
+
+        @staticmethod
+        def backward(ctx, gE):
+            gg, gt, gh, gJ = ctx.saved_tensors
+            return gE * gg, gE * gt, gE * gh, gE * gJ, None, None, None
+
+    return AnnealEnergy
+
+
+_AnnealEnergy = None
+
+
+def anneal_energy(gammas, ts, h, J, psi0, tol: float = 2.0 ** -23, ckpt_every: int = 0):
+    """Differentiable anneal energy: gammas, ts, h, J are float64 tensors
+    (requires_grad as needed); psi0 is a complex64 CUDA tensor."""
+    global _AnnealEnergy
+    if _AnnealEnergy is None:
+        _AnnealEnergy = _make_anneal_function()
+    return _AnnealEnergy.apply(gammas, ts, h, J, psi0, tol, ckpt_every)

@@ -38,66 +38,6 @@ void set_error(const std::string &msg) { g_err = msg; }
 // Kernels: energies, spectral bound, normalisation
 // ---------------------------------------------------------------------------
 
-// Q[lo] = sum_{j<k<LB} J_jk s_j(lo) s_k(lo).
-__global__ void k_qtable(EnergyTables T, double *Q)
-{
-    const uint32_t lo = blockIdx.x * blockDim.x + threadIdx.x;
-    if (lo >= (1u << T.LB)) return;
-    double acc = 0.0;
-    for (int j = 0; j < T.LB; ++j) {
-        const double sj = ((lo >> j) & 1) ? -1.0 : 1.0;
-        double fj = 0.0;
-        for (int k = j + 1; k < T.LB; ++k) {
-            const double Jk = T.J[pair_off(T.n, j, k)];
-            fj += ((lo >> k) & 1) ? -Jk : Jk;
-        }
-        acc += sj * fj;
-    }
-    Q[lo] = acc;
-}
-
-__device__ inline void block_minmax(double lo, double hi, double *part)
-{
-    __shared__ double smin[256], smax[256];
-    smin[threadIdx.x] = lo;
-    smax[threadIdx.x] = hi;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
-            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = smin[0];
-        part[2 * blockIdx.x + 1] = smax[0];
-    }
-}
-
-// Min / max of E over all z generated from the tables (grid-stride over tiles
-// of 2^LB consecutive indices).  256 threads.
-__global__ void __launch_bounds__(256) k_minmax_energy(EnergyTables T, double *part)
-{
-    __shared__ double f[LB_TAB];
-    __shared__ double Cc;
-    const uint64_t ntiles = uint64_t(1) << (T.n - T.LB);
-    const uint32_t TE = 1u << T.LB;
-    double mn = INFINITY, mx = -INFINITY;
-    for (uint64_t hi = blockIdx.x; hi < ntiles; hi += gridDim.x) {
-        __syncthreads();
-        tile_fields(T, hi, f, &Cc);
-        __syncthreads();
-        for (uint32_t lo = threadIdx.x; lo < TE; lo += blockDim.x) {
-            double e = Cc + T.Q[lo];
-            for (int j = 0; j < T.LB; ++j) e += ((lo >> j) & 1) ? -f[j] : f[j];
-            mn = fmin(mn, e);
-            mx = fmax(mx, e);
-        }
-    }
-    block_minmax(mn, mx, part);
-}
-
 template <typename R>
 __global__ void __launch_bounds__(256) k_minmax_diag(const R *d, uint64_t N, double *part)
 {
@@ -109,50 +49,6 @@ __global__ void __launch_bounds__(256) k_minmax_diag(const R *d, uint64_t N, dou
         mx = fmax(mx, v);
     }
     block_minmax(mn, mx, part);
-}
-
-__global__ void __launch_bounds__(256) k_minmax_final(const double *part, int np, double *out)
-{
-    double mn = INFINITY, mx = -INFINITY;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) {
-        mn = fmin(mn, part[2 * i]);
-        mx = fmax(mx, part[2 * i + 1]);
-    }
-    __shared__ double smin[256], smax[256];
-    smin[threadIdx.x] = mn;
-    smax[threadIdx.x] = mx;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
-            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        out[0] = smin[0];
-        out[1] = smax[0];
-    }
-}
-
-// d[z] = (E(z) - c) / r formed in double, rounded once to R.
-template <typename R>
-__global__ void __launch_bounds__(256) k_normalize_energy(EnergyTables T, double c, double inv_r, R *d)
-{
-    __shared__ double f[LB_TAB];
-    __shared__ double Cc;
-    const uint64_t ntiles = uint64_t(1) << (T.n - T.LB);
-    const uint32_t TE = 1u << T.LB;
-    for (uint64_t hi = blockIdx.x; hi < ntiles; hi += gridDim.x) {
-        __syncthreads();
-        tile_fields(T, hi, f, &Cc);
-        __syncthreads();
-        for (uint32_t lo = threadIdx.x; lo < TE; lo += blockDim.x) {
-            double e = Cc + T.Q[lo];
-            for (int j = 0; j < T.LB; ++j) e += ((lo >> j) & 1) ? -f[j] : f[j];
-            d[(hi << T.LB) | lo] = (R)((e - c) * inv_r);
-        }
-    }
 }
 
 template <typename R>
@@ -176,7 +72,7 @@ __global__ void k_qtilde(const double *Q, int LB, double inv_r, float *Qt)
 
 
 struct WsLayout {
-    size_t b1, b2, d, part, red, hj, q, qt, coef, items, total;
+    size_t b1, b2, d, part, red, hj, q, qt, coef, items, norms, total;
 };
 
 static WsLayout ws_layout(int n, int prec, bool otf)
@@ -196,6 +92,7 @@ static WsLayout ws_layout(int n, int prec, bool otf)
     L.qt = take((size_t(1) << LB_TAB) * sizeof(float));
     L.coef = (n <= Cfg<float>::TB) ? take((size_t)(KMAX_ONCHIP + 1) * cs) : size_t(-1);
     L.items = take(256);
+    L.norms = take(KMAX_MON * sizeof(double));
     L.total = off;
     return L;
 }
@@ -217,7 +114,7 @@ static qw_status setup_tables(int n, const double *h, const double *J, char *ws,
     T->n = n;
     T->LB = std::min(n, LB_TAB);
     const int nq = 1 << T->LB;
-    hipLaunchKernelGGL(k_qtable, dim3((nq + 255) / 256), dim3(256), 0, s, *T, const_cast<double *>(T->Q));
+    hipLaunchKernelGGL(k_qtable<0>, dim3((nq + 255) / 256), dim3(256), 0, s, *T, const_cast<double *>(T->Q));
     QW_HIP(hipGetLastError());
     QW_HIP(hipStreamSynchronize(s));  // hj lives on this stack frame
     return QW_OK;
@@ -237,10 +134,10 @@ static qw_status minmax(int n, const R *diag, const EnergyTables *T, char *ws, c
     } else {
         const uint64_t ntiles = uint64_t(1) << (n - T->LB);
         np = grid_for(ntiles, 1, MAXPART);
-        hipLaunchKernelGGL(k_minmax_energy, dim3(np), dim3(256), 0, s, *T, part);
+        hipLaunchKernelGGL(k_minmax_energy<0>, dim3(np), dim3(256), 0, s, *T, part);
     }
     QW_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(256), 0, s, part, np, red);
+    hipLaunchKernelGGL(k_minmax_final<0>, dim3(1), dim3(256), 0, s, part, np, red);
     QW_HIP(hipGetLastError());
     double h2[2];
     QW_HIP(hipMemcpyAsync(h2, red, sizeof(h2), hipMemcpyDeviceToHost, s));
@@ -311,6 +208,50 @@ static void launch_pass(const PassArgs<R> &a, bool start, bool otf, uint64_t nti
     } else {
         hipLaunchKernelGGL((k_pass<R, TB, NT, false, false>), dim3((unsigned)ntiles), dim3(NT), 0, s, a);
     }
+}
+
+// Read back ||b_k||^2 (k = 1..K-1), ||y||^2 (slot 0) and ||v||^2 (slot K+1);
+// fill the evaluation-error bound of section II.B.3,
+//   sum_k u||b_k|| + u||c_k v - b_{k+2}|| + sqrt(d) gamma_d ||b_{k+1}||,
+// using ||c_k v - b_{k+2}|| <= |c_k| ||v|| + ||b_{k+2}||, d = n + 1, and report
+// QW_EDIVERGE if a vector exceeds what a valid bound allows: with ||H~|| <= 1,
+// b_k = sum_{m>=k} c_m U_{m-k}(H~) v and |U_j| <= j + 1 on [-1, 1], so
+// ||b_k|| <= sum_{m>=k} |c_m| (m - k + 1) ||v||, and ||y|| <= (1 + tol) ||v||.
+static qw_status check_growth(int n, int K, const std::vector<double> &alpha, double tol, double u,
+                              const double *dnorms, hipStream_t s, qw_info *info)
+{
+    std::vector<double> sq(K + 2);
+    QW_HIP(hipMemcpyAsync(sq.data(), dnorms, sq.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    QW_HIP(hipStreamSynchronize(s));
+    const double nv = std::sqrt(sq[K + 1]);
+    std::vector<double> nb(K + 3, 0.0);
+    for (int k = 1; k < K; ++k) nb[k] = std::sqrt(sq[k]);
+    nb[K] = std::fabs(alpha[K]) * nv;
+    nb[0] = std::sqrt(sq[0]);
+    const double d = n + 1, gd = d * u / (1.0 - d * u);
+    double bound = 0.0;
+    for (int k = 0; k <= K; ++k)
+        bound += u * nb[k] + u * (std::fabs(alpha[k]) * nv + nb[k + 2]) + std::sqrt(d) * gd * nb[k + 1];
+    double worst = 0.0;   // max ratio of a norm to its a-priori limit
+    double tail = 0.0, tailw = 0.0;   // sum_{m>=k} |c_m| and sum_{m>=k} |c_m| (m - k + 1)
+    for (int k = K; k >= 1; --k) {
+        tailw += tail + std::fabs(alpha[k]);
+        tail += std::fabs(alpha[k]);
+        const double lim = tailw * nv * (1.0 + 1e-3) + 64.0 * u * nv;
+        if (k < K && lim > 0.0) worst = std::max(worst, nb[k] / lim);
+    }
+    worst = std::max(worst, nb[0] / ((1.0 + tol + 1e-3) * nv + 1e-300));
+    if (info) {
+        info->eval_bound = bound;
+        info->growth = worst;
+        info->out_norm = nb[0];
+    }
+    if (worst > 1.0) {
+        set_error("the Clenshaw vectors grew past the limit of a valid spectral bound (growth " +
+                  std::to_string(worst) + "): the given radius is too small");
+        return QW_EDIVERGE;
+    }
+    return QW_OK;
 }
 
 // Optional HIP-event timing of an action call: mark(0) before the setup,
@@ -388,7 +329,7 @@ struct PassTimer {
 template <typename R>
 static qw_status action_impl(int n, const R *diag, const double *h, const double *J, double gamma, double t,
                              const void *psi_in, void *psi_out, double tol, int method, void *workspace,
-                             size_t ws_bytes, void *stream, qw_info *info)
+                             size_t ws_bytes, void *stream, qw_info *info, const double *given_cr = nullptr)
 {
     using C = typename Cplx<R>::T;
     using V = CVec<R>;
@@ -409,8 +350,19 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
 
     EnergyTables T{};
     double c = 0.0, r = 0.0;
-    st = bound_impl<R>(n, diag, h, J, gamma, ws, L, s, &T, &c, &r);
-    if (st != QW_OK) return st;
+    const bool monitor = (info && info->monitor) || given_cr;
+    if (given_cr) {
+        c = given_cr[0];
+        r = given_cr[1];
+        if (!finite(c) || !(r > 0.0) || !finite(r)) { set_error("the given bound needs finite c and r > 0"); return QW_EINVAL; }
+        if (!diag) {
+            st = setup_tables(n, h, J, ws, L, s, &T);
+            if (st != QW_OK) return st;
+        }
+    } else {
+        st = bound_impl<R>(n, diag, h, J, gamma, ws, L, s, &T, &c, &r);
+        if (st != QW_OK) return st;
+    }
 
     // g = gamma / r; in single precision round g towards zero and take
     // r = gamma / g, which is still a bound and makes g exact in float.
@@ -427,9 +379,10 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     const int eg = grid_for(nvec, 256 * 4, 1 << 16);
 
     if (info) {
-        const int want = info->timing;
+        const int want = info->timing, mon = info->monitor;
         std::memset(info, 0, sizeof(*info));
         info->timing = want;
+        info->monitor = mon;
         info->n = n;
         info->shift_c = c;
         info->radius_r = r;
@@ -475,10 +428,10 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         info->K = K;
         info->a = a;
         info->trunc_bound = err;
-        info->passes = (n <= Cfg<R>::TB) ? 1 : (int)plan.size();
+        info->passes = (int)plan.size();
     }
 
-    if (n <= Cfg<R>::TB) {
+    if (n <= Cfg<R>::TB && !monitor) {
         // on-chip: whole recurrence in one workgroup
         if (K > KMAX_ONCHIP) { set_error("degree too large for the on-chip path"); return QW_ENOMEM; }
         std::vector<C> ch(K + 1);
@@ -514,6 +467,13 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
 
     C *B1 = reinterpret_cast<C *>(ws + L.b1);
     C *B2 = reinterpret_cast<C *>(ws + L.b2);
+    double *norms = reinterpret_cast<double *>(ws + L.norms);
+    if (monitor) {
+        if (K + 2 > KMAX_MON) { set_error("degree too large for the norm monitor"); return QW_ENOMEM; }
+        QW_HIP(hipMemsetAsync(norms, 0, (K + 2) * sizeof(double), s));
+        hipLaunchKernelGGL(k_norm2<R>, dim3(grid_for(nvec, 256 * 8, 4096)), dim3(256), 0, s,
+                           reinterpret_cast<const V *>(psi), nvec, norms + K + 1);
+    }
     timer.mark(1);
     {
         double cr, ci;
@@ -551,6 +511,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
             pa.L = plan[p].L;
             pa.g0 = plan[p].g0;
             pa.h = plan[p].h;
+            pa.norm_acc = (monitor && last) ? norms + k : nullptr;
             const uint64_t ntiles = N >> (plan[p].L + plan[p].h);
             launch_pass<R>(pa, p == 0, otf, ntiles, s);
             ptimer.mark();
@@ -560,7 +521,10 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     }
     qw_status tst = timer.finish(info);
     if (tst != QW_OK) return tst;
-    return ptimer.finish(info, P);
+    tst = ptimer.finish(info, P);
+    if (tst != QW_OK || !monitor) return tst;
+    return check_growth(n, K, alpha, tol, sizeof(R) == 4 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53), norms, s,
+                        info);
 }
 
 template <typename R>
@@ -672,6 +636,25 @@ qw_status qw_expm_action_c128(int n, const double *diag, const double *h, const 
 {
     return action_impl<double>(n, diag, h, J, gamma, t, psi_in, psi_out, tol, (int)method, workspace, ws_bytes,
                                stream, info);
+}
+
+qw_status qw_expm_action_c64_bounded(int n, const float *diag, const double *h, const double *J, double gamma,
+                                     double t, double c, double r, const void *psi_in, void *psi_out, double tol,
+                                     qw_method method, void *workspace, size_t ws_bytes, void *stream, qw_info *info)
+{
+    const double cr[2] = {c, r};
+    return action_impl<float>(n, diag, h, J, gamma, t, psi_in, psi_out, tol, (int)method, workspace, ws_bytes,
+                              stream, info, cr);
+}
+
+qw_status qw_expm_action_c128_bounded(int n, const double *diag, const double *h, const double *J, double gamma,
+                                      double t, double c, double r, const void *psi_in, void *psi_out, double tol,
+                                      qw_method method, void *workspace, size_t ws_bytes, void *stream,
+                                      qw_info *info)
+{
+    const double cr[2] = {c, r};
+    return action_impl<double>(n, diag, h, J, gamma, t, psi_in, psi_out, tol, (int)method, workspace, ws_bytes,
+                               stream, info, cr);
 }
 
 // Host-only self check of the pass index maps; returns the number of passes or

@@ -35,10 +35,138 @@ static constexpr int ONCHIP_NT = 1024;
 static constexpr int MAXPART = 4096;          // reduction partials
 static constexpr int KMAX_ONCHIP = 1 << 17;   // coefficient slots for on-chip runs
 static constexpr int LB_TAB = 13;             // low bits of the energy tables
+static constexpr int KMAX_MON = 1 << 16;      // norm-monitor slots (degree limit when monitoring)
+
+// ---------------------------------------------------------------------------
+// Kernels: Ising energies and their range
+// ---------------------------------------------------------------------------
+
+// Q[lo] = sum_{j<k<LB} J_jk s_j(lo) s_k(lo).
+template <int D = 0>
+__global__ void k_qtable(EnergyTables T, double *Q)
+{
+    const uint32_t lo = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lo >= (1u << T.LB)) return;
+    double acc = 0.0;
+    for (int j = 0; j < T.LB; ++j) {
+        const double sj = ((lo >> j) & 1) ? -1.0 : 1.0;
+        double fj = 0.0;
+        for (int k = j + 1; k < T.LB; ++k) {
+            const double Jk = T.J[pair_off(T.n, j, k)];
+            fj += ((lo >> k) & 1) ? -Jk : Jk;
+        }
+        acc += sj * fj;
+    }
+    Q[lo] = acc;
+}
+
+__device__ inline void block_minmax(double lo, double hi, double *part)
+{
+    __shared__ double smin[256], smax[256];
+    smin[threadIdx.x] = lo;
+    smax[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = smin[0];
+        part[2 * blockIdx.x + 1] = smax[0];
+    }
+}
+
+// Min / max of E over all z generated from the tables (grid-stride over tiles
+// of 2^LB consecutive indices).  256 threads.
+template <int D = 0>
+__global__ void __launch_bounds__(256) k_minmax_energy(EnergyTables T, double *part)
+{
+    __shared__ double f[LB_TAB];
+    __shared__ double Cc;
+    const uint64_t ntiles = uint64_t(1) << (T.n - T.LB);
+    const uint32_t TE = 1u << T.LB;
+    double mn = INFINITY, mx = -INFINITY;
+    for (uint64_t hi = blockIdx.x; hi < ntiles; hi += gridDim.x) {
+        __syncthreads();
+        tile_fields(T, hi, f, &Cc);
+        __syncthreads();
+        for (uint32_t lo = threadIdx.x; lo < TE; lo += blockDim.x) {
+            double e = Cc + T.Q[lo];
+            for (int j = 0; j < T.LB; ++j) e += ((lo >> j) & 1) ? -f[j] : f[j];
+            mn = fmin(mn, e);
+            mx = fmax(mx, e);
+        }
+    }
+    block_minmax(mn, mx, part);
+}
+
+template <int D = 0>
+__global__ void __launch_bounds__(256) k_minmax_final(const double *part, int np, double *out)
+{
+    double mn = INFINITY, mx = -INFINITY;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        mn = fmin(mn, part[2 * i]);
+        mx = fmax(mx, part[2 * i + 1]);
+    }
+    __shared__ double smin[256], smax[256];
+    smin[threadIdx.x] = mn;
+    smax[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = smin[0];
+        out[1] = smax[0];
+    }
+}
+
+// d[z] = (E(z) - c) / r formed in double, rounded once to R.
+template <typename R>
+__global__ void __launch_bounds__(256) k_normalize_energy(EnergyTables T, double c, double inv_r, R *d)
+{
+    __shared__ double f[LB_TAB];
+    __shared__ double Cc;
+    const uint64_t ntiles = uint64_t(1) << (T.n - T.LB);
+    const uint32_t TE = 1u << T.LB;
+    for (uint64_t hi = blockIdx.x; hi < ntiles; hi += gridDim.x) {
+        __syncthreads();
+        tile_fields(T, hi, f, &Cc);
+        __syncthreads();
+        for (uint32_t lo = threadIdx.x; lo < TE; lo += blockDim.x) {
+            double e = Cc + T.Q[lo];
+            for (int j = 0; j < T.LB; ++j) e += ((lo >> j) & 1) ? -f[j] : f[j];
+            d[(hi << T.LB) | lo] = (R)((e - c) * inv_r);
+        }
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Kernels: Clenshaw recurrence
 // ---------------------------------------------------------------------------
+
+// Sum of one double per thread over the block, added atomically to *dst by
+// thread 0 (vector atomic on global memory).  Every thread must call it.
+__device__ inline void block_sum_atomic(double x, double *dst)
+{
+    __shared__ double wsum[16];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) wsum[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < nw; ++i) s += wsum[i];
+        atomicAdd(dst, s);
+    }
+}
 
 // b1 = c_K psi, b2 = 0   (Eq. recursion: b_K = c_K v, b_{K+1} = 0)
 template <typename R>
@@ -61,6 +189,20 @@ __global__ void __launch_bounds__(256) k_init(const CVec<R> *psi, CVec<R> *b1, C
     }
 }
 
+// *acc += ||x||^2 (double), grid-stride.
+template <typename R>
+__global__ void __launch_bounds__(256) k_norm2(const CVec<R> *x, uint64_t nvec, double *acc)
+{
+    double s = 0.0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nvec;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const CVec<R> p = x[i];
+#pragma unroll
+        for (int v = 0; v < CVec<R>::N; ++v) s += (double)p.v[v].x * p.v[v].x + (double)p.v[v].y * p.v[v].y;
+    }
+    block_sum_atomic(s, acc);
+}
+
 // out = (cr + i ci) psi   (K = 0 or a zero spectral bound)
 template <typename R>
 __global__ void __launch_bounds__(256) k_scale(const CVec<R> *psi, CVec<R> *out, R cr, R ci, uint64_t nvec)
@@ -81,18 +223,20 @@ __global__ void __launch_bounds__(256) k_scale(const CVec<R> *psi, CVec<R> *out,
 template <typename R> struct PassArgs {
     using C = typename Cplx<R>::T;
     const C *b1;   // b_{k+1}: its flips over the tile's group are summed
-    const C *acc;  // START: b_{k+2};  ADD: the partial b_k
+    const C *acc;  // START: b_{k+2} (NULL: zero);  ADD: the partial b_k
     C *dst;        // output, may alias acc
     const C *psi;  // START: v
     const R *d;    // START: normalised diagonal (unless on the fly)
     const float *Qt;   // on the fly: Q / r table over the low 13 bits
     const double *hJ;  // on the fly: h then J (device)
     double otf_c, otf_inv_r;
+    R dscale = R(1);   // START: the diagonal used is d * dscale
     R g;           // gamma / r
     R scale;       // 2 inside the recurrence, 1 for the final step
     R cr, ci;      // START: c_k
     R pr, pi;      // multiplier of the result (the global phase on the last pass)
     int n, L, g0, h;
+    double *norm_acc = nullptr;   // if set: += sum |dst|^2 over the tile (atomic, one per block)
 };
 
 // One pass of one Clenshaw term over one tile (see tile_base/tile_index).
@@ -134,7 +278,12 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
         if (e < TE) {
             const uint64_t idx = tile_index(base, e, a.L, a.g0);
             own[q] = *reinterpret_cast<const V *>(a.b1 + idx);
-            accv[q] = *reinterpret_cast<const V *>(a.acc + idx);
+            if (a.acc) {
+                accv[q] = *reinterpret_cast<const V *>(a.acc + idx);
+            } else {
+#pragma unroll
+                for (int v = 0; v < VE; ++v) accv[q].v[v] = C{R(0), R(0)};
+            }
             if constexpr (START) {
                 psiv[q] = *reinterpret_cast<const V *>(a.psi + idx);
                 if constexpr (!OTF) {
@@ -147,6 +296,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
         }
     }
     __syncthreads();
+    double nrm = 0.0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
@@ -171,7 +321,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                         for (int j = 0; j < LB_TAB; ++j) s += ((ee >> j) & 1) ? -fld[j] : fld[j];
                         dd = (R)s;
                     } else {
-                        dd = dv[q][v];
+                        dd = dv[q][v] * a.dscale;
                     }
                     const C b = own[q].v[v], ac = accv[q].v[v], ps = psiv[q].v[v];
                     const R hr = dd * b.x + a.g * sr;
@@ -188,8 +338,14 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                 out.v[v].y = a.pr * o.y + a.pi * o.x;
             }
             *reinterpret_cast<V *>(a.dst + idx) = out;
+            if (a.norm_acc) {
+#pragma unroll
+                for (int v = 0; v < VE; ++v)
+                    nrm += (double)out.v[v].x * out.v[v].x + (double)out.v[v].y * out.v[v].y;
+            }
         }
     }
+    if (a.norm_acc) block_sum_atomic(nrm, a.norm_acc);
 }
 
 template <typename R, int TB, int NT, bool START, bool OTF>

@@ -1,0 +1,139 @@
+"""GPU parity of the anneal energy gradient (qw_anneal_energy_grad_c64).
+
+The single-precision adjoint is compared with the FP64 oracle adjoint (O4),
+itself pinned to Daleckii-Krein and finite differences on the CPU; tolerance
+1e-4 relative L2 per parameter group (gamma, h, J; 1e-3 for t at 20 qubits,
+see GRAD_TOL_T) and 1e-5 on the energy.
+The 20-qubit, 16-segment workload is compared with stored oracle values
+(tests/golden/grad_n20_s16.json, written by tests/golden/make_grad_golden.py).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+GRAD_TOL = 1e-4
+# dE/dt_s is Re<ybar, -i H psi_s>: the imaginary part of an inner product whose
+# real part is about r |ybar| (10^3 - 10^4 times larger at 20 qubits), so the
+# ~1e-6 relative error of the complex64 forward states is amplified by that
+# factor; the bar for the t group is set from it.
+GRAD_TOL_T = 1e-3
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2608_12058_amd as qw
+    assert torch.cuda.is_available()
+    qw.lib()
+    return torch, qw
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu_grad(env, n, h, J, gam, ts, psi0, ckpt=0, tol=2.0 ** -23):
+    torch, qw = env
+    x = torch.as_tensor(psi0).to(torch.complex64).cuda()
+    return qw.anneal_energy_grad(h, J, gam, ts, x, tol=tol, ckpt_every=ckpt)
+
+
+@pytest.mark.parametrize("n,S,ckpt", [(5, 3, 0), (9, 4, 2), (14, 3, 0), (14, 3, 3), (16, 5, 1), (17, 4, 7)])
+def test_grad_vs_oracle_adjoint(env, oracle_mod, n, S, ckpt):
+    h, J = synth.sk_instance(n, 40 + n)
+    gam = np.linspace(1.8, 0.1, S)
+    ts = np.full(S, 0.45)
+    psi0 = synth.plus_state(n)
+    E_ref, g_ref = oracle_mod.anneal_energy_grad(n, h, J, gam, ts, psi0, 1e-13)
+    E, g, info = gpu_grad(env, n, h, J, gam, ts, psi0, ckpt)
+    assert abs(E - E_ref) <= 1e-5 * abs(E_ref)
+    for key in ("gamma", "t", "h", "J"):
+        assert rel(g[key], g_ref[key]) <= GRAD_TOL, (key, g[key][:4], g_ref[key][:4])
+
+
+def test_grad_vs_daleckii_krein(env, oracle_mod):
+    n = 5
+    h, J = synth.sk_instance(n, 13)
+    gam = np.array([1.5, 0.9, 0.2])
+    ts = np.array([0.5, 0.7, 0.4])
+    psi0 = synth.plus_state(n)
+    E_ref, g_ref = oracle_mod.anneal_grad_daleckii_krein(n, h, J, gam, ts, psi0)
+    E, g, _ = gpu_grad(env, n, h, J, gam, ts, psi0)
+    assert abs(E - E_ref) <= 1e-5 * abs(E_ref)
+    for key in ("gamma", "t", "h", "J"):
+        assert rel(g[key], g_ref[key]) <= GRAD_TOL, key
+
+
+def test_checkpoint_intervals_agree(env):
+    n, S = 15, 3
+    h, J = synth.sk_instance(n, 77)
+    gam, ts = np.array([1.2, 0.7, 0.3]), np.array([0.6, 0.6, 0.6])
+    psi0 = synth.random_state(n, 77)
+    res = [gpu_grad(env, n, h, J, gam, ts, psi0, c) for c in (0, 1, 4, 1000)]
+    for E, g, _ in res[1:]:
+        assert E == res[0][0]
+        for key in ("gamma", "t", "h", "J"):
+            assert np.array_equal(g[key], res[0][1][key]), key
+
+
+def test_forward_state_matches_action(env, oracle_mod):
+    """psi_S returned by the gradient call equals chaining the action calls."""
+    torch, qw = env
+    n, S = 16, 4
+    h, J = synth.sk_instance(n, 5)
+    gam, ts = np.linspace(1.5, 0.2, S), np.full(S, 0.5)
+    x = synth.plus_state_torch(n, "cuda", torch.complex64)
+    psiT = torch.empty_like(x)
+    qw.anneal_energy_grad(h, J, gam, ts, x, psiT_out=psiT)
+    y = x.clone()
+    for gg, tt in zip(gam, ts):
+        y, _ = qw.expm_action(y, float(gg), float(tt), h=h, J=J)
+    assert torch.max(torch.abs(y - psiT)).item() < 1e-5
+    E_ref, states, Ed = oracle_mod.anneal_forward(n, h, J, gam, ts, synth.plus_state(n), 1e-13)
+    assert rel(psiT.cpu().numpy().astype(np.complex128), states[-1]) < 1e-5
+
+
+def test_autograd_function(env):
+    torch, qw = env
+    n, S = 10, 3
+    h, J = synth.sk_instance(n, 3)
+    gam = torch.tensor([1.4, 0.8, 0.2], dtype=torch.float64, requires_grad=True)
+    ts = torch.tensor([0.5, 0.5, 0.5], dtype=torch.float64, requires_grad=True)
+    ht = torch.tensor(h, requires_grad=True)
+    Jt = torch.tensor(J, requires_grad=True)
+    x = synth.plus_state_torch(n, "cuda", torch.complex64)
+    E = qw.anneal_energy(gam, ts, ht, Jt, x)
+    (3.0 * E).backward()
+    E2, g, _ = qw.anneal_energy_grad(h, J, gam.detach().numpy(), ts.detach().numpy(), x)
+    assert abs(E.item() - E2) < 1e-12
+    assert np.allclose(gam.grad.numpy(), 3.0 * g["gamma"])
+    assert np.allclose(Jt.grad.numpy(), 3.0 * g["J"])
+
+
+def test_config4_n20_s16_vs_golden(env):
+    """20 qubits, 16 segments (gamma 2 -> 0.05, t_s = 0.5), complex64 forward,
+    single-precision adjoint, against the stored FP64 oracle gradient; the
+    stored finite differences pin the oracle at this size."""
+    torch, qw = env
+    with open(os.path.join(HERE, "golden", "grad_n20_s16.json")) as f:
+        gold = json.load(f)
+    n, S = gold["n"], gold["S"]
+    h, J = synth.sk_instance(n, gold["seed"])
+    gam, ts = np.array(gold["schedule"]["gamma"]), np.array(gold["schedule"]["t"])
+    x = synth.plus_state_torch(n, "cuda", torch.complex64)
+    E, g, info = qw.anneal_energy_grad(h, J, gam, ts, x, ckpt_every=8, timing=1)
+    errs = {key: rel(g[key], gold["grad"][key]) for key in ("gamma", "t", "h", "J")}
+    print(f"config4: E {E:.8f} (oracle {gold['E']:.8f}), group errors {errs}, {info}")
+    assert abs(E - gold["E"]) <= 1e-5 * abs(gold["E"])
+    for key, err in errs.items():
+        assert err <= (GRAD_TOL_T if key == "t" else GRAD_TOL), key
+    for name, val in gold["fd"].items():
+        key, i = name[:-1].split("[")
+        assert abs(gold["grad"][key][int(i)] - val) <= 5e-5 * max(1.0, abs(val)), name

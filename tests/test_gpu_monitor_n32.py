@@ -1,0 +1,123 @@
+"""GPU tests of the norm monitor / caller-given bound (evaluation-error bound of
+section II.B.3, divergence status) and of the 32-qubit on-the-fly diagonal
+(sampled closed forms and time reversal at N = 2^32)."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2608_12058_amd as qw
+    assert torch.cuda.is_available()
+    qw.lib()
+    return torch, qw
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("prec,n", [(64, 11), (64, 18), (128, 16)])
+def test_monitor_bound_holds(env, oracle_mod, prec, n):
+    """The measured error stays below truncation + coefficient + the paper's
+    evaluation bound computed from the fused norms."""
+    torch, qw = env
+    dt = torch.complex64 if prec == 64 else torch.complex128
+    tol = 2.0 ** -23 if prec == 64 else 1e-12
+    h, J = synth.sk_instance(n, 90 + n)
+    E = oracle_mod.energies(n, h, J)
+    psi = synth.random_state(n, 90)
+    ref = oracle_mod.expm_action(n, E, 0.9, 3.0, psi, 1e-13)
+    x = torch.as_tensor(psi).to(dt).cuda()
+    y, info = qw.expm_action(x, 0.9, 3.0, h=h, J=J, tol=tol, monitor=True)
+    y = y.cpu().numpy().astype(np.complex128)
+    err = np.linalg.norm(y - ref)
+    u = 2.0 ** -24 if prec == 64 else 2.0 ** -53
+    assert 0 < info["eval_bound"]
+    assert info["growth"] <= 1.0
+    assert abs(info["out_norm"] - 1.0) < 1e-5
+    # the float diagonal adds a representation error (about a * u) that the
+    # paper's bound for an exact H does not contain
+    rep = info["a"] * u * 4 if prec == 64 else 0.0
+    assert err <= tol + info["K"] * 2.0 ** -53 + info["eval_bound"] + rep
+
+
+@pytest.mark.parametrize("prec", [64, 128])
+def test_given_bound_matches_and_small_radius_diverges(env, oracle_mod, prec):
+    torch, qw = env
+    dt = torch.complex64 if prec == 64 else torch.complex128
+    tol = 2.0 ** -23 if prec == 64 else 1e-12
+    n = 15
+    h, J = synth.sk_instance(n, 7)
+    E = oracle_mod.energies(n, h, J)
+    c, r = oracle_mod.spectral_shift_radius(E, n, 1.0)
+    psi = torch.as_tensor(synth.plus_state(n)).to(dt).cuda()
+    y_auto, _ = qw.expm_action(psi, 1.0, 2.0, h=h, J=J, tol=tol)
+    y_given, info = qw.expm_action(psi, 1.0, 2.0, h=h, J=J, tol=tol, bound=(c, r * 1.25))
+    assert info["growth"] <= 1.0
+    err = (torch.linalg.vector_norm(y_given - y_auto) / torch.linalg.vector_norm(y_auto)).item()
+    assert err <= (1e-5 if prec == 64 else 1e-12)
+    with pytest.raises(qw.QwError) as ei:
+        qw.expm_action(psi, 1.0, 2.0, h=h, J=J, tol=tol, bound=(c, r * 0.5))
+    assert ei.value.status == qw.QW_EDIVERGE
+    with pytest.raises(qw.QwError) as ei:
+        qw.expm_action(psi, 1.0, 2.0, h=h, J=J, tol=tol, bound=(c, 0.0))
+    assert ei.value.status == qw.QW_EINVAL
+
+
+N32 = 32
+
+
+def test_n32_gamma0_on_the_fly_diagonal(env, oracle_mod):
+    """gamma = 0 at 32 qubits: exp(-i t E(z)) on |+>, the diagonal recomputed
+    per tile and term; 512 sampled amplitudes against E(z) summed by its
+    definition for each sampled z."""
+    torch, qw = env
+    h, J = synth.sk_instance(N32, 0)
+    psi = synth.plus_state_torch(N32, "cuda", torch.complex64)
+    y, info = qw.expm_action(psi, 0.0, 1.0, h=h, J=J, out=psi)
+    assert info["passes"] == 4
+    rng = np.random.default_rng(32)
+    idx = np.concatenate([[0, (1 << N32) - 1], rng.integers(0, 1 << N32, 510)])
+    got = y[torch.as_tensor(idx, device="cuda")].cpu().numpy().astype(np.complex128)
+    amp = np.full(len(idx), 1.0 / np.sqrt(2.0 ** N32), dtype=np.complex128)
+    ref = oracle_mod.closed_form_gamma0_amps(N32, h, J, 1.0, amp, idx)
+    assert rel(got, ref) <= 1e-5
+    del y, psi
+    torch.cuda.empty_cache()
+
+
+def test_n32_hp0_product_state(env, oracle_mod):
+    torch, qw = env
+    f = synth.product_state_factors(N32, 33)
+    psi = synth.product_state_torch(f, "cuda", torch.complex64)
+    zh, zJ = np.zeros(N32), np.zeros(N32 * (N32 - 1) // 2)
+    y, _ = qw.expm_action(psi, 0.9, 1.0, h=zh, J=zJ, out=psi)
+    rng = np.random.default_rng(33)
+    idx = rng.integers(0, 1 << N32, 2048)
+    got = y[torch.as_tensor(idx, device="cuda")].cpu().numpy().astype(np.complex128)
+    ref = oracle_mod.closed_form_hp0_product_amps(f, 0.9, 1.0, idx)
+    assert rel(got, ref) <= 1e-5
+    del y, psi
+    torch.cuda.empty_cache()
+
+
+def test_n32_time_reversal(env):
+    """SK seed 0, gamma = 1: U(-t) U(t) |+> = |+> and the norm is kept."""
+    torch, qw = env
+    h, J = synth.sk_instance(N32, 0)
+    x = synth.plus_state_torch(N32, "cuda", torch.complex64)
+    y, _ = qw.expm_action(x, 1.0, 0.5, h=h, J=J, out=x)
+    nrm = torch.linalg.vector_norm(y).item()
+    assert abs(nrm - 1.0) < 1e-5
+    y, _ = qw.expm_action(y, 1.0, -0.5, h=h, J=J, out=y)
+    amp = 1.0 / np.sqrt(2.0 ** N32)
+    err = (torch.linalg.vector_norm(y - amp) / 1.0).item()
+    assert err < 2e-5
+    del y, x
+    torch.cuda.empty_cache()
