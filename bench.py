@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-c128", action="store_true")
     ap.add_argument("--cpu-terms", type=int, default=30, help="Clenshaw terms of the CPU oracle sample")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-config2", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--n32", action="store_true", help="also time the 32-qubit on-the-fly workload (~1 min)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -73,6 +74,32 @@ def cpu_baseline(n, h, J, gamma, t, tol, terms):
     return {"value": (1 << n) * terms / sec, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{terms} Clenshaw terms of the same {n}-qubit instance, complex128 plain C loops "
                       f"({sec:.1f} s)"}
+
+
+def config2_leg(torch, qw, synth):
+    """24-qubit SK (seed 0, gamma = 0.8, t = 10, |+>): time to solution of the
+    complex64 recurrence with Chebyshev and CF coefficients at 2^-23 and of the
+    complex128 recurrence at 1e-12 and at 1e-6 (same workload, same GPU)."""
+    n = 24
+    h, J = synth.sk_instance(n, 0)
+    out = {}
+    for name, dt, tol, method in (("c64_cheb_2m23", torch.complex64, 2.0 ** -23, "cheb"),
+                                  ("c64_cf_2m23", torch.complex64, 2.0 ** -23, "cf"),
+                                  ("c128_cheb_1e-12", torch.complex128, 1e-12, "cheb"),
+                                  ("c128_cheb_1e-6", torch.complex128, 1e-6, "cheb")):
+        psi = synth.plus_state_torch(n, "cuda", dt)
+        o = torch.empty_like(psi)
+        ws = qw.Workspace.for_problem(n, 64 if dt == torch.complex64 else 128)
+        qw.expm_action(psi, 0.8, 10.0, h=h, J=J, tol=tol, method=method, out=o, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = qw.expm_action(psi, 0.8, 10.0, h=h, J=J, tol=tol, method=method, out=o, workspace=ws, timing=1)
+        torch.cuda.synchronize()
+        out[name] = {"K": info["K"], "ms": (time.perf_counter() - t0) * 1e3, "loop_ms": info["loop_ms"],
+                     "trunc_bound": info["trunc_bound"]}
+        del psi, o, ws
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched_leg(torch, qw, synth, np):
@@ -259,6 +286,9 @@ def main():
         del ws128, psi128, out128
         torch.cuda.empty_cache()
 
+    if not args.no_config2:
+        log("[bench] n=24: complex64 Chebyshev / CF at 2^-23 vs complex128 at 1e-12")
+        result["config2"] = config2_leg(torch, qw, synth)
     if not args.no_batched:
         log("[bench] batched: 256 SK instances, n ~ U{12..22}")
         result["batched"] = batched_leg(torch, qw, synth, np)
