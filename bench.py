@@ -235,9 +235,13 @@ def main():
     term_ms = loop_ms / terms
     alg_bytes_term = BYTES_PER_AMP_TERM[64] * N
     achieved = (BYTES_INIT[64] * N + alg_bytes_term * terms) / (loop_ms * 1e-3) / 1e9
-    pass_bytes = [36 * N] + [24 * N] * (P - 1)      # bytes each pass actually moves
-    passes = [{"pass": p, "avg_us": pass_ms[p] / terms * 1e3, "moved_bytes": pass_bytes[p],
-               "moved_GBps": pass_bytes[p] / (pass_ms[p] / terms * 1e-3) / 1e9} for p in range(P)]
+    # bytes each orientation moves per term under the fused schedule: the two
+    # end orientations alternate a fused pass (44 B/amp; 40 on the fly) every
+    # other term, the middle ones add (24 B/amp) every term
+    fused_b = 44 * N
+    per_term = [fused_b / 2 if p in (0, P - 1) else 24 * N for p in range(P)] if P > 1 else [36 * N]
+    passes = [{"orientation": p, "avg_us_per_term": pass_ms[p] / terms * 1e3, "moved_bytes_per_term": per_term[p],
+               "moved_GBps": per_term[p] / (pass_ms[p] / terms * 1e-3) / 1e9} for p in range(P)]
 
     traffic = None
     if os.path.exists(args.traffic_json):

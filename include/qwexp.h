@@ -247,6 +247,12 @@ const char *qw_last_error(void);
  * Launches nothing. */
 int qw_debug_check_plan(int n, int precision);
 
+/* Host-only: the sequence of Clenshaw passes for degree K >= 1 over P
+ * orientations, as quadruples (mode 0 START / 1 ADD / 2 FUSED, orientation,
+ * term k, final flag) written to out (4*cap ints).  Returns the number of
+ * passes; nothing is written when it exceeds cap.  Launches nothing. */
+int qw_debug_schedule(int K, int P, int *out, int cap);
+
 /* Library version string. */
 const char *qw_version(void);
 

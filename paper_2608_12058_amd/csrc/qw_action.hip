@@ -59,12 +59,6 @@ __global__ void __launch_bounds__(256) k_normalize_diag(const R *E, uint64_t N, 
         d[i] = (R)(((double)E[i] - c) * inv_r);
 }
 
-// Q~ = Q / r rounded to float, for the per-term diagonal of the on-the-fly form.
-__global__ void k_qtilde(const double *Q, int LB, double inv_r, float *Qt)
-{
-    const uint32_t lo = blockIdx.x * blockDim.x + threadIdx.x;
-    if (lo < (1u << LB)) Qt[lo] = (float)(Q[lo] * inv_r);
-}
 
 // ---------------------------------------------------------------------------
 // Host side
@@ -89,7 +83,7 @@ static WsLayout ws_layout(int n, int prec, bool otf)
     L.red = take(2 * sizeof(double));
     L.hj = take((32 + 32 * 31 / 2) * sizeof(double));
     L.q = take((size_t(1) << LB_TAB) * sizeof(double));
-    L.qt = take((size_t(1) << LB_TAB) * sizeof(float));
+    L.qt = take(4 * (size_t(1) << LB_TAB) * sizeof(float));   // one pair table per orientation
     L.coef = (n <= Cfg<float>::TB) ? take((size_t)(KMAX_ONCHIP + 1) * cs) : size_t(-1);
     L.items = take(256);
     L.norms = take(KMAX_MON * sizeof(double));
@@ -194,20 +188,17 @@ static qw_status bound_impl(int n, const R *diag, const double *h, const double 
 }
 
 template <typename R>
-static void launch_pass(const PassArgs<R> &a, bool start, bool otf, uint64_t ntiles, hipStream_t s)
+static void launch_pass(const PassArgs<R> &a, int mode, bool otf, uint64_t ntiles, hipStream_t s)
 {
     constexpr int TB = Cfg<R>::TB, NT = Cfg<R>::NT;
-    if (start) {
-        if constexpr (sizeof(R) == 4) {
-            if (otf) {
-                hipLaunchKernelGGL((k_pass<R, TB, NT, true, true>), dim3((unsigned)ntiles), dim3(NT), 0, s, a);
-                return;
-            }
-        }
-        hipLaunchKernelGGL((k_pass<R, TB, NT, true, false>), dim3((unsigned)ntiles), dim3(NT), 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_pass<R, TB, NT, false, false>), dim3((unsigned)ntiles), dim3(NT), 0, s, a);
+    const dim3 grid((unsigned)ntiles), block(NT);
+    if constexpr (sizeof(R) == 4) {
+        if (otf && mode == PM_START) { hipLaunchKernelGGL((k_pass<R, TB, NT, PM_START, true>), grid, block, 0, s, a); return; }
+        if (otf && mode == PM_FUSED) { hipLaunchKernelGGL((k_pass<R, TB, NT, PM_FUSED, true>), grid, block, 0, s, a); return; }
     }
+    if (mode == PM_START) hipLaunchKernelGGL((k_pass<R, TB, NT, PM_START, false>), grid, block, 0, s, a);
+    else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass<R, TB, NT, PM_FUSED, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_pass<R, TB, NT, PM_ADD, false>), grid, block, 0, s, a);
 }
 
 // Read back ||b_k||^2 (k = 1..K-1), ||y||^2 (slot 0) and ||v||^2 (slot K+1);
@@ -289,12 +280,13 @@ struct EventTimer {
     }
 };
 
-// timing == 2: an event after every pass; pass_ms[p] sums the durations of
-// pass p over all terms (the final step included).
+// timing == 2: an event after every pass; pass_ms[o] sums the durations of
+// the passes over orientation o of the plan (the final step included).
 struct PassTimer {
     bool on;
     hipStream_t s;
     std::vector<hipEvent_t> ev;
+    std::vector<int> slot;
     size_t used = 0;
     PassTimer(bool on_, hipStream_t s_, size_t count) : on(on_), s(s_)
     {
@@ -308,19 +300,23 @@ struct PassTimer {
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
     }
-    void mark()
+    void mark(int sl)
     {
-        if (on && used < ev.size()) (void)hipEventRecord(ev[used++], s);
+        if (on && used < ev.size()) {
+            (void)hipEventRecord(ev[used++], s);
+            slot.push_back(sl);
+        }
     }
-    qw_status finish(qw_info *info, int P)
+    qw_status finish(qw_info *info)
     {
-        if (!on) return QW_OK;
+        if (!on || used < 2) return QW_OK;
         QW_HIP(hipEventSynchronize(ev[used - 1]));
         for (int p = 0; p < 4; ++p) info->pass_ms[p] = 0.f;
         for (size_t i = 1; i < used; ++i) {
             float ms = 0.f;
             QW_HIP(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
-            info->pass_ms[(i - 1) % P] += ms;
+            const int sl = slot[i];
+            if (sl >= 0 && sl < 4) info->pass_ms[sl] += ms;
         }
         return QW_OK;
     }
@@ -409,8 +405,6 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
             hipLaunchKernelGGL(k_normalize_energy<R>, dim3(grid_for(N >> T.LB, 1, 1 << 16)), dim3(256), 0, s,
                                T, c, inv_r, dn);
         }
-    } else {
-        hipLaunchKernelGGL(k_qtilde, dim3((1 << LB_TAB) / 256), dim3(256), 0, s, T.Q, LB_TAB, inv_r, qt);
     }
     QW_HIP(hipGetLastError());
 
@@ -465,8 +459,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         return timer.finish(info);
     }
 
-    C *B1 = reinterpret_cast<C *>(ws + L.b1);
-    C *B2 = reinterpret_cast<C *>(ws + L.b2);
+    C *X = reinterpret_cast<C *>(ws + L.b1);
+    C *Y = reinterpret_cast<C *>(ws + L.b2);
     double *norms = reinterpret_cast<double *>(ws + L.norms);
     if (monitor) {
         if (K + 2 > KMAX_MON) { set_error("degree too large for the norm monitor"); return QW_ENOMEM; }
@@ -474,54 +468,81 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         hipLaunchKernelGGL(k_norm2<R>, dim3(grid_for(nvec, 256 * 8, 4096)), dim3(256), 0, s,
                            reinterpret_cast<const V *>(psi), nvec, norms + K + 1);
     }
+    const int P = (int)plan.size();
+    if (otf) {
+        for (int o = 0; o < P; ++o)
+            hipLaunchKernelGGL(k_qtable_orient<0>, dim3((1 << LB_TAB) / 256), dim3(256), 0, s, T.h, n, plan[o].L,
+                               plan[o].g0, plan[o].h, inv_r, qt + (size_t)o * (1 << LB_TAB));
+    }
     timer.mark(1);
     {
+        // b_K = c_K psi (b_{K+1} = 0 is never read: the first pass takes acc = NULL)
         double cr, ci;
         coef_of(alpha, K, cr, ci);
-        hipLaunchKernelGGL(k_init<R>, dim3(eg), dim3(256), 0, s, reinterpret_cast<const V *>(psi),
-                           reinterpret_cast<V *>(B1), reinterpret_cast<V *>(B2), (R)cr, (R)ci, nvec);
+        hipLaunchKernelGGL(k_scale<R>, dim3(eg), dim3(256), 0, s, reinterpret_cast<const V *>(psi),
+                           reinterpret_cast<V *>(X), (R)cr, (R)ci, nvec);
         QW_HIP(hipGetLastError());
     }
     PassArgs<R> pa{};
     pa.psi = psi;
     pa.d = dn;
-    pa.Qt = qt;
     pa.hJ = T.h;
     pa.otf_c = c;
     pa.otf_inv_r = inv_r;
     pa.g = (R)g;
     pa.n = n;
-    const int P = (int)plan.size();
-    PassTimer ptimer(info && info->timing == 2, s, K * P + 1);
-    ptimer.mark();
-    for (int k = K - 1; k >= 0; --k) {
-        double cr, ci;
-        coef_of(alpha, k, cr, ci);
-        const bool fin = (k == 0);
-        for (int p = 0; p < P; ++p) {
-            pa.b1 = B1;
-            pa.acc = B2;
-            const bool last = (p == P - 1);
-            pa.dst = (fin && last) ? out : B2;
-            pa.scale = fin ? R(1) : R(2);
-            pa.cr = (R)cr;
-            pa.ci = (R)ci;
-            pa.pr = (fin && last) ? (R)ph_r : R(1);
-            pa.pi = (fin && last) ? (R)ph_i : R(0);
-            pa.L = plan[p].L;
-            pa.g0 = plan[p].g0;
-            pa.h = plan[p].h;
-            pa.norm_acc = (monitor && last) ? norms + k : nullptr;
-            const uint64_t ntiles = N >> (plan[p].L + plan[p].h);
-            launch_pass<R>(pa, p == 0, otf, ntiles, s);
-            ptimer.mark();
+    const std::vector<SchedPass> sched = fused_schedule(K, P);
+    PassTimer ptimer(info && info->timing == 2, s, sched.size() + 1);
+    ptimer.mark(-1);
+    auto scale_of = [](int k) { return k == 0 ? R(1) : R(2); };
+    for (const SchedPass &sp : sched) {
+        const PassPlan &pl = plan[sp.orient];
+        double cr = 0.0, ci = 0.0;
+        pa.b1 = X;
+        pa.L = pl.L;
+        pa.g0 = pl.g0;
+        pa.h = pl.h;
+        pa.Qt = qt + (size_t)sp.orient * (1 << LB_TAB);
+        pa.pr = R(1);
+        pa.pi = R(0);
+        pa.dst2 = nullptr;
+        pa.norm_acc = nullptr;
+        if (sp.mode == PM_START) {
+            coef_of(alpha, sp.k, cr, ci);
+            pa.acc = (sp.k == K - 1) ? nullptr : Y;
+            pa.dst = sp.fin ? out : Y;
+            pa.scale = scale_of(sp.k);
+            if (sp.fin) { pa.pr = (R)ph_r; pa.pi = (R)ph_i; }
+            if (monitor && P == 1) pa.norm_acc = norms + sp.k;
+        } else if (sp.mode == PM_ADD) {
+            pa.acc = Y;
+            pa.dst = sp.fin ? out : Y;
+            pa.scale = scale_of(sp.k);
+            if (sp.fin) {
+                pa.pr = (R)ph_r;
+                pa.pi = (R)ph_i;
+                if (monitor) pa.norm_acc = norms;
+            }
+        } else {
+            coef_of(alpha, sp.k - 1, cr, ci);
+            pa.acc = Y;
+            pa.dst = Y;
+            pa.dst2 = X;
+            pa.scale = scale_of(sp.k);
+            pa.scale2 = scale_of(sp.k - 1);
+            if (monitor) pa.norm_acc = norms + sp.k;
         }
-        QW_HIP(hipGetLastError());
-        std::swap(B1, B2);
+        pa.cr = (R)cr;
+        pa.ci = (R)ci;
+        const uint64_t ntiles = N >> (pl.L + pl.h);
+        launch_pass<R>(pa, sp.mode, otf, ntiles, s);
+        ptimer.mark(sp.orient);
+        if (sp.mode == PM_FUSED || (sp.mode == PM_START && P == 1)) std::swap(X, Y);
     }
+    QW_HIP(hipGetLastError());
     qw_status tst = timer.finish(info);
     if (tst != QW_OK) return tst;
-    tst = ptimer.finish(info, P);
+    tst = ptimer.finish(info);
     if (tst != QW_OK || !monitor) return tst;
     return check_growth(n, K, alpha, tol, sizeof(R) == 4 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53), norms, s,
                         info);
@@ -580,7 +601,7 @@ using namespace qw;
 extern "C" {
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.1 (gfx950)"; }
+const char *qw_version(void) { return "qwexp 0.2 (gfx950, fused passes)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {
@@ -655,6 +676,22 @@ qw_status qw_expm_action_c128_bounded(int n, const double *diag, const double *h
     const double cr[2] = {c, r};
     return action_impl<double>(n, diag, h, J, gamma, t, psi_in, psi_out, tol, (int)method, workspace, ws_bytes,
                                stream, info, cr);
+}
+
+// Host-only: the pass sequence for degree K and P orientations as (mode,
+// orientation, k, fin) quadruples; returns the number of passes (or the
+// capacity needed when cap is too small).
+int qw_debug_schedule(int K, int P, int *out, int cap)
+{
+    const std::vector<SchedPass> S = fused_schedule(K, P);
+    if ((int)S.size() <= cap && out)
+        for (size_t i = 0; i < S.size(); ++i) {
+            out[4 * i] = S[i].mode;
+            out[4 * i + 1] = S[i].orient;
+            out[4 * i + 2] = S[i].k;
+            out[4 * i + 3] = S[i].fin;
+        }
+    return (int)S.size();
 }
 
 // Host-only self check of the pass index maps; returns the number of passes or

@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(Cfg<float>::NT) k_pass_batched(const BatchDesc
         a.L = TB - a.h;
         a.g0 = TB;
     }
-    pass_tile<float, TB, Cfg<float>::NT, START, false>(a, (uint64_t)tt.y, lds);
+    pass_tile<float, TB, Cfg<float>::NT, START ? PM_START : PM_ADD, false>(a, (uint64_t)tt.y, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -497,9 +497,9 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
         pa.dscale = (float)sp.inv_r;
         const uint64_t ntiles = N >> (plan[p].L + plan[p].h);
         if (p == 0)
-            hipLaunchKernelGGL((k_pass<float, GTB, GNT, true, false>), dim3((unsigned)ntiles), dim3(GNT), 0, s, pa);
+            hipLaunchKernelGGL((k_pass<float, GTB, GNT, PM_START, false>), dim3((unsigned)ntiles), dim3(GNT), 0, s, pa);
         else
-            hipLaunchKernelGGL((k_pass<float, GTB, GNT, false, false>), dim3((unsigned)ntiles), dim3(GNT), 0, s, pa);
+            hipLaunchKernelGGL((k_pass<float, GTB, GNT, PM_ADD, false>), dim3((unsigned)ntiles), dim3(GNT), 0, s, pa);
     };
     const int eg_grid = grid_for(N / 2, 256 * 4, 1 << 16);
     const uint32_t TEw = (uint32_t)std::min<uint64_t>(N, uint64_t(1) << GTB);

@@ -220,58 +220,123 @@ __global__ void __launch_bounds__(256) k_scale(const CVec<R> *psi, CVec<R> *out,
     }
 }
 
+enum PassMode { PM_START = 0, PM_ADD = 1, PM_FUSED = 2 };
+
 template <typename R> struct PassArgs {
     using C = typename Cplx<R>::T;
     const C *b1;   // b_{k+1}: its flips over the tile's group are summed
-    const C *acc;  // START: b_{k+2} (NULL: zero);  ADD: the partial b_k
-    C *dst;        // output, may alias acc
-    const C *psi;  // START: v
-    const R *d;    // START: normalised diagonal (unless on the fly)
-    const float *Qt;   // on the fly: Q / r table over the low 13 bits
+    const C *acc;  // START: b_{k+2} (NULL: zero);  ADD, FUSED: the partial b_k
+    C *dst;        // START, ADD: output (may alias acc);  FUSED: the completed b_k
+    C *dst2;       // FUSED: the partial b_{k-1} (may alias b1)
+    const C *psi;  // START, FUSED: v
+    const R *d;    // START, FUSED: normalised diagonal (unless on the fly)
+    const float *Qt;   // on the fly: Q / r table of this orientation (2^(L+h) entries)
     const double *hJ;  // on the fly: h then J (device)
     double otf_c, otf_inv_r;
-    R dscale = R(1);   // START: the diagonal used is d * dscale
+    R dscale = R(1);   // the diagonal used is d * dscale
     R g;           // gamma / r
-    R scale;       // 2 inside the recurrence, 1 for the final step
-    R cr, ci;      // START: c_k
-    R pr, pi;      // multiplier of the result (the global phase on the last pass)
+    R scale;       // START, ADD: 2 inside the recurrence, 1 for the final step; FUSED: for b_k
+    R scale2;      // FUSED: the same for b_{k-1}
+    R cr, ci;      // START: c_k;  FUSED: c_{k-1}
+    R pr, pi;      // START, ADD: multiplier of the result (the global phase on the last pass)
     int n, L, g0, h;
-    double *norm_acc = nullptr;   // if set: += sum |dst|^2 over the tile (atomic, one per block)
+    double *norm_acc = nullptr;   // if set: += sum |b|^2 of the completed vector (atomic, one per block)
 };
 
-// One pass of one Clenshaw term over one tile (see tile_base/tile_index).
-//  START: dst = scale * (d .* b1 + g * F_group b1) - acc + c_k psi
-//  ADD:   dst = acc + scale * g * F_group b1
-// then dst *= (pr + i pi).  F_group sums the flips of the tile's h group bits.
-template <typename R, int TB, int NT, bool START, bool OTF>
+// Fields of the on-the-fly diagonal for a tile of any orientation: tile
+// element bit i stands for index bit vb(i) (i < L: bit i; else g0 + i - L);
+// the other index bits are fixed by `base`.  Threads 0..L+h-1 compute
+//   f_i = h_vb(i) + sum_{u fixed} J_{vb(i) u} s_u,
+// thread L+h the constant C = sum_{u fixed} h_u s_u + sum_{u<w fixed} J_uw s_u s_w.
+// With the orientation's pair table Q[e] = sum_{i<j} J_{vb(i) vb(j)} s_i(e) s_j(e),
+// E = C + Q[e] + sum_i f_i s_i(e).
+__device__ inline void tile_fields_orient(const double *hJ, int n, int L, int g0, int h, uint64_t base,
+                                          double *f, double *Cc)
+{
+    const double *hh = hJ, *J = hJ + n;
+    const int nv = L + h, t = threadIdx.x;
+    auto isvar = [&](int u) { return u < L || (u >= g0 && u < g0 + h); };
+    if (t < nv) {
+        const int j = (t < L) ? t : g0 + (t - L);
+        double acc = hh[j];
+        for (int u = 0; u < n; ++u) {
+            if (isvar(u)) continue;
+            const double Jju = J[pair_off(n, j < u ? j : u, j < u ? u : j)];
+            acc += ((base >> u) & 1) ? -Jju : Jju;
+        }
+        f[t] = acc;
+    } else if (t == nv) {
+        double acc = 0.0;
+        for (int u = 0; u < n; ++u) {
+            if (isvar(u)) continue;
+            double fu = hh[u];
+            for (int w = u + 1; w < n; ++w) {
+                if (isvar(w)) continue;
+                const double Jw = J[pair_off(n, u, w)];
+                fu += ((base >> w) & 1) ? -Jw : Jw;
+            }
+            acc += ((base >> u) & 1) ? -fu : fu;
+        }
+        *Cc = acc;
+    }
+}
+
+// Pair table of one orientation, scaled: Qt[e] = Q[e] / r in float.
+template <int D = 0>
+__global__ void k_qtable_orient(const double *hJ, int n, int L, int g0, int h, double inv_r, float *Qt)
+{
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nv = L + h;
+    if (e >= (1u << nv)) return;
+    const double *J = hJ + n;
+    double acc = 0.0;
+    for (int i = 0; i < nv; ++i) {
+        const int vi = (i < L) ? i : g0 + (i - L);
+        double fi = 0.0;
+        for (int j = i + 1; j < nv; ++j) {
+            const int vj = (j < L) ? j : g0 + (j - L);
+            const double Jij = J[pair_off(n, vi, vj)];
+            fi += ((e >> j) & 1) ? -Jij : Jij;
+        }
+        acc += ((e >> i) & 1) ? -fi : fi;
+    }
+    Qt[e] = (float)(acc * inv_r);
+}
+
+// One pass over one tile (see tile_base/tile_index); F_group sums the flips of
+// the tile's h group bits:
+//  START: dst = scale (d .* b1 + g F b1) - acc + c_k psi,            then *= (pr + i pi)
+//  ADD:   dst = acc + scale g F b1,                                   then *= (pr + i pi)
+//  FUSED: b_k = acc + scale g F b1 (completes term k) -> dst;
+//         dst2 = scale2 (d .* b_k + g F b_k) - b1 + c_{k-1} psi (first part of term k-1)
+// FUSED needs b_k of the whole tile, so the tile is re-staged through LDS.
+template <typename R, int TB, int NT, int MODE, bool OTF>
 __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, typename Cplx<R>::T *lds)
 {
     using C = typename Cplx<R>::T;
     using V = CVec<R>;
     constexpr int VE = V::N;
     constexpr int PER = (1 << TB) / (NT * VE);
+    constexpr bool DIAG = (MODE != PM_ADD);
     static_assert(PER >= 1, "tile smaller than one vector per thread");
     __shared__ float fld[OTF ? LB_TAB : 1];
     __shared__ float fbase;
 
-    const uint32_t TE = 1u << (a.L + a.h);
+    const int nv = a.L + a.h;
+    const uint32_t TE = 1u << nv;
     const uint64_t base = tile_base(tile, a.L, a.g0, a.h);
 
     if constexpr (OTF) {
-        // Per-tile fields of the diagonal: the tile is the contiguous block of
-        // the low 13 bits, so its high bits are fixed (the tile id).
         __shared__ double f64[LB_TAB];
         __shared__ double c64;
-        EnergyTables T{a.hJ, a.hJ + a.n, nullptr, a.n, LB_TAB};
-        tile_fields(T, tile, f64, &c64);
+        tile_fields_orient(a.hJ, a.n, a.L, a.g0, a.h, base, f64, &c64);
         __syncthreads();
-        if (threadIdx.x < LB_TAB) fld[threadIdx.x] = (float)(f64[threadIdx.x] * a.otf_inv_r);
+        if ((int)threadIdx.x < nv) fld[threadIdx.x] = (float)(f64[threadIdx.x] * a.otf_inv_r);
         if (threadIdx.x == 0) fbase = (float)((c64 - a.otf_c) * a.otf_inv_r);
     }
 
     V own[PER], accv[PER];
-    V psiv[START ? PER : 1];
-    R dv[START ? PER : 1][VE];
+    V psiv[DIAG ? PER : 1];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
@@ -284,75 +349,148 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
 #pragma unroll
                 for (int v = 0; v < VE; ++v) accv[q].v[v] = C{R(0), R(0)};
             }
-            if constexpr (START) {
-                psiv[q] = *reinterpret_cast<const V *>(a.psi + idx);
-                if constexpr (!OTF) {
-#pragma unroll
-                    for (int v = 0; v < VE; ++v) dv[q][v] = a.d[idx + v];
-                }
-            }
+            if constexpr (DIAG) psiv[q] = *reinterpret_cast<const V *>(a.psi + idx);
 #pragma unroll
             for (int v = 0; v < VE; ++v) lds[e + v] = own[q].v[v];
         }
     }
     __syncthreads();
-    double nrm = 0.0;
+
+    // Flip sums of the VE consecutive elements e..e+VE-1 (e a multiple of VE).
+    // A flip of tile bit >= log2(VE) maps the group onto another aligned group,
+    // read from LDS as one 16-byte vector; a flip of bit 0 (complex64 only)
+    // swaps the two elements of the group, which this thread holds in `self`.
+    auto flips = [&](uint32_t e, const V &self, R (&sr)[VE], R (&si)[VE]) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
-        if (e < TE) {
-            const uint64_t idx = tile_index(base, e, a.L, a.g0);
-            V out;
+        for (int v = 0; v < VE; ++v) {
+            sr[v] = R(0);
+            si[v] = R(0);
+        }
+        const V *lv = reinterpret_cast<const V *>(lds);
+        for (int j = 0; j < a.h; ++j) {
+            const uint32_t m = 1u << (a.L + j);
+            if (VE == 2 && m == 1u) {
+                sr[0] += self.v[VE - 1].x;
+                si[0] += self.v[VE - 1].y;
+                sr[VE - 1] += self.v[0].x;
+                si[VE - 1] += self.v[0].y;
+            } else {
+                const V nb = lv[(e ^ m) / VE];
 #pragma unroll
-            for (int v = 0; v < VE; ++v) {
-                const uint32_t ee = e + v;
-                R sr = R(0), si = R(0);
-                for (int j = 0; j < a.h; ++j) {
-                    const C nb = lds[ee ^ (1u << (a.L + j))];
-                    sr += nb.x;
-                    si += nb.y;
+                for (int v = 0; v < VE; ++v) {
+                    sr[v] += nb.v[v].x;
+                    si[v] += nb.v[v].y;
                 }
-                C o;
-                if constexpr (START) {
-                    R dd;
-                    if constexpr (OTF) {
-                        float s = fbase + a.Qt[ee];
-#pragma unroll
-                        for (int j = 0; j < LB_TAB; ++j) s += ((ee >> j) & 1) ? -fld[j] : fld[j];
-                        dd = (R)s;
-                    } else {
-                        dd = dv[q][v] * a.dscale;
-                    }
-                    const C b = own[q].v[v], ac = accv[q].v[v], ps = psiv[q].v[v];
-                    const R hr = dd * b.x + a.g * sr;
-                    const R hi = dd * b.y + a.g * si;
-                    o.x = (a.scale * hr - ac.x) + (a.cr * ps.x - a.ci * ps.y);
-                    o.y = (a.scale * hi - ac.y) + (a.cr * ps.y + a.ci * ps.x);
-                } else {
-                    const C ac = accv[q].v[v];
-                    const R sg = a.scale * a.g;
-                    o.x = ac.x + sg * sr;
-                    o.y = ac.y + sg * si;
-                }
-                out.v[v].x = a.pr * o.x - a.pi * o.y;
-                out.v[v].y = a.pr * o.y + a.pi * o.x;
             }
-            *reinterpret_cast<V *>(a.dst + idx) = out;
-            if (a.norm_acc) {
+        }
+    };
+    // Diagonal of element ee (global index idx): loaded from d (after the
+    // barrier, to keep it out of the registers held across it) or rebuilt from
+    // the tile fields.
+    auto diag_of = [&](uint64_t idx, uint32_t ee) -> R {
+        if constexpr (OTF) {
+            float s = fbase + a.Qt[ee];
+            for (int j = 0; j < nv; ++j) s += ((ee >> j) & 1) ? -fld[j] : fld[j];
+            return (R)s;
+        } else {
+            return a.d[idx] * a.dscale;
+        }
+    };
+
+    double nrm = 0.0;
+    if constexpr (MODE == PM_FUSED) {
+        // complete b_k in registers
 #pragma unroll
-                for (int v = 0; v < VE; ++v)
-                    nrm += (double)out.v[v].x * out.v[v].x + (double)out.v[v].y * out.v[v].y;
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
+            if (e < TE) {
+                R sr[VE], si[VE];
+                flips(e, own[q], sr, si);
+                const R sg = a.scale * a.g;
+#pragma unroll
+                for (int v = 0; v < VE; ++v) {
+                    accv[q].v[v].x += sg * sr[v];
+                    accv[q].v[v].y += sg * si[v];
+                }
+            }
+        }
+        __syncthreads();   // every flip of b_{k+1} has been read
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
+            if (e < TE) {
+#pragma unroll
+                for (int v = 0; v < VE; ++v) lds[e + v] = accv[q].v[v];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
+            if (e < TE) {
+                const uint64_t idx = tile_index(base, e, a.L, a.g0);
+                V out;
+                R sr[VE], si[VE];
+                flips(e, accv[q], sr, si);
+#pragma unroll
+                for (int v = 0; v < VE; ++v) {
+                    const R dd = diag_of(idx + v, e + v);
+                    const C bk = accv[q].v[v], bp = own[q].v[v], ps = psiv[q].v[v];
+                    const R hr = dd * bk.x + a.g * sr[v];
+                    const R hi = dd * bk.y + a.g * si[v];
+                    out.v[v].x = (a.scale2 * hr - bp.x) + (a.cr * ps.x - a.ci * ps.y);
+                    out.v[v].y = (a.scale2 * hi - bp.y) + (a.cr * ps.y + a.ci * ps.x);
+                    if (a.norm_acc) nrm += (double)bk.x * bk.x + (double)bk.y * bk.y;
+                }
+                *reinterpret_cast<V *>(a.dst + idx) = accv[q];
+                *reinterpret_cast<V *>(a.dst2 + idx) = out;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
+            if (e < TE) {
+                const uint64_t idx = tile_index(base, e, a.L, a.g0);
+                V out;
+                R sr_[VE], si_[VE];
+                flips(e, own[q], sr_, si_);
+#pragma unroll
+                for (int v = 0; v < VE; ++v) {
+                    const uint32_t ee = e + v;
+                    const R sr = sr_[v], si = si_[v];
+                    C o;
+                    if constexpr (MODE == PM_START) {
+                        const R dd = diag_of(idx + v, ee);
+                        const C b = own[q].v[v], ac = accv[q].v[v], ps = psiv[q].v[v];
+                        const R hr = dd * b.x + a.g * sr;
+                        const R hi = dd * b.y + a.g * si;
+                        o.x = (a.scale * hr - ac.x) + (a.cr * ps.x - a.ci * ps.y);
+                        o.y = (a.scale * hi - ac.y) + (a.cr * ps.y + a.ci * ps.x);
+                    } else {
+                        const C ac = accv[q].v[v];
+                        const R sg = a.scale * a.g;
+                        o.x = ac.x + sg * sr;
+                        o.y = ac.y + sg * si;
+                    }
+                    out.v[v].x = a.pr * o.x - a.pi * o.y;
+                    out.v[v].y = a.pr * o.y + a.pi * o.x;
+                    if (a.norm_acc) nrm += (double)out.v[v].x * out.v[v].x + (double)out.v[v].y * out.v[v].y;
+                }
+                *reinterpret_cast<V *>(a.dst + idx) = out;
             }
         }
     }
     if (a.norm_acc) block_sum_atomic(nrm, a.norm_acc);
 }
 
-template <typename R, int TB, int NT, bool START, bool OTF>
-__global__ void __launch_bounds__(NT) k_pass(PassArgs<R> a)
+// Two 512-thread workgroups share a CU (64 KB of LDS each): registers are
+// capped so that both fit (4 waves per SIMD).
+template <typename R, int TB, int NT, int MODE, bool OTF>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_pass(PassArgs<R> a)
 {
     __shared__ typename Cplx<R>::T lds[1 << TB];
-    pass_tile<R, TB, NT, START, OTF>(a, blockIdx.x, lds);
+    pass_tile<R, TB, NT, MODE, OTF>(a, blockIdx.x, lds);
 }
 
 // Whole recurrence of one small instance (n <= TB) inside one workgroup.
@@ -503,6 +641,35 @@ inline int grid_for(uint64_t work, int per_block, int cap)
 }
 
 template <typename R> constexpr int prec_of() { return sizeof(R) == 4 ? 64 : 128; }
+
+// Pass sequence of one call.  Term k (K-1 .. 0) visits the P orientations of
+// the plan in order 0..P-1 when K-1-k is even and in reverse when it is odd,
+// so the last orientation of term k is the first of term k-1 and the two are
+// done by one FUSED pass.  P = 1: every term is one START pass.
+struct SchedPass {
+    int mode;    // PassMode
+    int orient;  // index into the pass plan
+    int k;       // term completed (FUSED), started (START) or extended (ADD)
+    int fin;     // 1 on the pass that writes the final output
+};
+
+inline std::vector<SchedPass> fused_schedule(int K, int P)
+{
+    std::vector<SchedPass> S;
+    if (K < 1 || P < 1) return S;
+    auto orient = [&](int k, int i) { return (((K - 1 - k) & 1) == 0) ? i : P - 1 - i; };
+    if (P == 1) {
+        for (int k = K - 1; k >= 0; --k) S.push_back({PM_START, 0, k, k == 0 ? 1 : 0});
+        return S;
+    }
+    S.push_back({PM_START, orient(K - 1, 0), K - 1, 0});
+    for (int k = K - 1; k >= 0; --k) {
+        for (int i = 1; i <= P - 2; ++i) S.push_back({PM_ADD, orient(k, i), k, 0});
+        if (k == 0) S.push_back({PM_ADD, orient(0, P - 1), 0, 1});
+        else S.push_back({PM_FUSED, orient(k, P - 1), k, 0});
+    }
+    return S;
+}
 
 // c_k = (-i)^k alpha_k as (re, im).
 inline void coef_of(const std::vector<double> &alpha, int k, double &cr, double &ci)
