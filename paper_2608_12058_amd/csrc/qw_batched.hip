@@ -7,11 +7,11 @@
 //  * instances with n <= 13 run their whole recurrence inside one workgroup
 //    (vector resident in LDS): one persistent launch drains them in
 //    descending order of cost N*K;
-//  * instances with 14 <= n <= 22 run the two-pass Clenshaw term of the
-//    single-instance path, grouped: instances are sorted by degree K so that
-//    at global step s the still-active ones form a prefix of one tile table,
-//    and each step is two launches over that prefix.  The launches are
-//    captured into a HIP graph.  Optionally the large instances are split into
+//  * instances with 14 <= n <= 22 run the fused two-orientation schedule of the
+//    single-instance path (one pass per Clenshaw term), grouped: instances are
+//    sorted by degree K so that at global step s the still-active ones form a
+//    prefix of one tile table, and each step is one launch over that prefix.
+//    The launches are captured into a HIP graph.  Optionally the large instances are split into
 //    "waves" whose working set (20 bytes per amplitude) fits the 256 MB
 //    last-level cache, each wave running all of its steps before the next; the
 //    wave size is picked by qw_batched_tune_c64 and stored in a tune file.
@@ -132,7 +132,8 @@ __global__ void __launch_bounds__(256) k_minmax_instances(const BatchDesc *D, co
     }
 }
 
-// b1 = c_K psi, b2 = 0 over one 2^13 tile of a large instance.
+// b1 = c_K psi over one 2^13 tile of a large instance (b_{K+1} = 0 is never
+// read: the first pass takes no accumulator).
 __global__ void __launch_bounds__(256) k_init_batched(const BatchDesc *D, const int2 *tiles)
 {
     const int2 tt = tiles[blockIdx.x];
@@ -142,46 +143,76 @@ __global__ void __launch_bounds__(256) k_init_batched(const BatchDesc *D, const 
     for (uint32_t e = threadIdx.x; e < (1u << Cfg<float>::TB); e += blockDim.x) {
         const float2 p = b.psi[base + e];
         b.B1[base + e] = make_float2(cK.x * p.x - cK.y * p.y, cK.x * p.y + cK.y * p.x);
-        b.B2[base + e] = make_float2(0.f, 0.f);
     }
 }
 
-// One pass of the global step `step` for the tile (instance, t) of this block:
-// the instance is at term k = K - 1 - step (k = 0: the final step).
-template <bool START>
-__global__ void __launch_bounds__(Cfg<float>::NT) k_pass_batched(const BatchDesc *D, const int2 *tiles, int step)
+// Global step `step` of the fused two-orientation schedule for the tile
+// (instance, t) of this block.  Every instance with 14 <= n <= 22 runs
+// K + 1 passes: step 0 starts term K-1 in the low orientation (MODE START);
+// step j (1 <= j < K) completes term K-j and starts term K-j-1 in one fused
+// pass; step K completes term 0 and writes the output (MODE ADD).  The
+// orientation alternates (even steps: the low 13 bits, odd steps: the n-13
+// high bits), so it is the same for every active instance of a step; the
+// host launches the fused and the final instances of a step separately.
+// 1024 threads per workgroup (16 waves, one workgroup per CU): the per-instance
+// arguments live in vector registers here, so fewer amplitudes per thread keep
+// the fused pass free of spills.
+static constexpr int BNT = 1024;
+
+template <bool HIGH, int MODE>
+__global__ void __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(4)))
+k_pass_batched(const BatchDesc *D, const int2 *tiles, int step)
 {
-    constexpr int TB = Cfg<float>::TB;
+    constexpr int TB = Cfg<float>::TB, NT = BNT;
     __shared__ float2 lds[1 << TB];
-    const int2 tt = tiles[blockIdx.x];
-    const BatchDesc &b = D[tt.x];
-    const int k = b.K - 1 - step;
-    const bool fin = (k == 0);
-    const bool last = !START;                   // two passes: START then ADD
+    const int2 tt = wave_uniform(tiles[blockIdx.x]);
+    const BatchDesc b = wave_uniform(D[tt.x]);
+    const bool swapped = (step >= 1) && ((step - 1) & 1);   // one swap after every fused step
+    float2 *X = swapped ? b.B2 : b.B1;
+    float2 *Y = swapped ? b.B1 : b.B2;
     PassArgs<float> a{};
-    a.b1 = (step & 1) ? b.B2 : b.B1;
-    a.acc = (step & 1) ? b.B1 : b.B2;
-    a.dst = (fin && last) ? b.out : const_cast<float2 *>(a.acc);
+    a.b1 = X;
     a.psi = b.psi;
     a.d = b.d;
     a.g = b.g;
-    a.scale = fin ? 1.f : 2.f;
-    const float2 ck = b.coef[k];
-    a.cr = ck.x;
-    a.ci = ck.y;
-    a.pr = (fin && last) ? b.pr : 1.f;
-    a.pi = (fin && last) ? b.pi : 0.f;
     a.n = b.n;
-    if (START) {
-        a.L = 0;
-        a.g0 = 0;
-        a.h = TB;
-    } else {
+    a.pr = 1.f;
+    a.pi = 0.f;
+    if (HIGH) {
         a.h = b.n - TB;
         a.L = TB - a.h;
         a.g0 = TB;
+    } else {
+        a.L = 0;
+        a.g0 = 0;
+        a.h = TB;
     }
-    pass_tile<float, TB, Cfg<float>::NT, START ? PM_START : PM_ADD, false>(a, (uint64_t)tt.y, lds);
+    if constexpr (MODE == PM_START) {
+        const int k = b.K - 1;
+        const float2 ck = b.coef[k];
+        a.acc = nullptr;
+        a.dst = Y;
+        a.scale = (k == 0) ? 1.f : 2.f;
+        a.cr = ck.x;
+        a.ci = ck.y;
+    } else if constexpr (MODE == PM_ADD) {
+        a.acc = Y;
+        a.dst = b.out;
+        a.scale = 1.f;
+        a.pr = b.pr;
+        a.pi = b.pi;
+    } else {
+        const int k = b.K - step;   // completed here; k - 1 is started
+        const float2 ck = b.coef[k - 1];
+        a.acc = Y;
+        a.dst = Y;
+        a.dst2 = X;
+        a.scale = 2.f;
+        a.scale2 = (k - 1 == 0) ? 1.f : 2.f;
+        a.cr = ck.x;
+        a.ci = ck.y;
+    }
+    pass_tile<float, TB, NT, MODE, false>(a, (uint64_t)tt.y, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -475,7 +506,8 @@ static qw_status batched_impl(const qw_batch_item *items, int count, const doubl
     }
     std::vector<int2> tiles;
     tiles.reserve(P.n_tiles);
-    struct WaveSched { int tile_begin; std::vector<int> prefix; };   // prefix[s]: active tiles at step s
+    // prefix[j]: tiles of the instances still active at step j (K >= j)
+    struct WaveSched { int tile_begin; std::vector<int> prefix; };
     std::vector<WaveSched> sched;
     for (auto &w : waves) {
         std::sort(w.begin(), w.end(), [&](int a, int b) { return run.K[a] > run.K[b]; });
@@ -487,10 +519,10 @@ static qw_status batched_impl(const qw_batch_item *items, int count, const doubl
             cum.push_back((int)tiles.size() - ws_.tile_begin);
         }
         const int maxK = run.K[w.front()];
-        ws_.prefix.resize(maxK);
+        ws_.prefix.resize(maxK + 1);
         size_t j = w.size();
-        for (int st = 0; st < maxK; ++st) {
-            while (j > 0 && run.K[w[j - 1]] < st + 1) --j;   // instances with K >= st+1 are active
+        for (int st = 0; st <= maxK; ++st) {
+            while (j > 0 && run.K[w[j - 1]] < st) --j;
             ws_.prefix[st] = (j > 0) ? cum[j - 1] : 0;
         }
         sched.push_back(std::move(ws_));
@@ -518,13 +550,29 @@ static qw_status batched_impl(const qw_batch_item *items, int count, const doubl
             const int2 *wt = dT + w.tile_begin;
             hipLaunchKernelGGL(k_init_batched, dim3(w.prefix[0]), dim3(256), 0, s, (const BatchDesc *)dD, wt);
             run.launches++;
-            for (int st = 0; st < (int)w.prefix.size(); ++st) {
-                const int nb = w.prefix[st];
-                hipLaunchKernelGGL(k_pass_batched<true>, dim3(nb), dim3(Cfg<float>::NT), 0, s,
-                                   (const BatchDesc *)dD, wt, st);
-                hipLaunchKernelGGL(k_pass_batched<false>, dim3(nb), dim3(Cfg<float>::NT), 0, s,
-                                   (const BatchDesc *)dD, wt, st);
-                run.launches += 2;
+            const int last = (int)w.prefix.size() - 1;   // = the largest K of the wave
+            auto launch = [&](int mode, bool high, int begin, int count, int st) {
+                if (count <= 0) return;
+                const dim3 g(count), bl(BNT);
+                const int2 *t0 = wt + begin;
+                const BatchDesc *dd = dD;
+                if (mode == PM_START) hipLaunchKernelGGL((k_pass_batched<false, PM_START>), g, bl, 0, s, dd, t0, st);
+                else if (mode == PM_FUSED && high) hipLaunchKernelGGL((k_pass_batched<true, PM_FUSED>), g, bl, 0, s, dd, t0, st);
+                else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass_batched<false, PM_FUSED>), g, bl, 0, s, dd, t0, st);
+                else if (high) hipLaunchKernelGGL((k_pass_batched<true, PM_ADD>), g, bl, 0, s, dd, t0, st);
+                else hipLaunchKernelGGL((k_pass_batched<false, PM_ADD>), g, bl, 0, s, dd, t0, st);
+                run.launches++;
+            };
+            for (int st = 0; st <= last; ++st) {
+                const bool high = (st & 1) != 0;
+                if (st == 0) {
+                    launch(PM_START, false, 0, w.prefix[0], 0);
+                    continue;
+                }
+                // instances with K > st fuse, those with K == st finish
+                const int nfuse = (st + 1 <= last) ? w.prefix[st + 1] : 0;
+                launch(PM_FUSED, high, 0, nfuse, st);
+                launch(PM_ADD, high, nfuse, w.prefix[st] - nfuse, st);
             }
         }
         if (use_graph) {

@@ -152,6 +152,21 @@ __global__ void __launch_bounds__(256) k_normalize_energy(EnergyTables T, double
 // Kernels: Clenshaw recurrence
 // ---------------------------------------------------------------------------
 
+// A value every lane of the wave holds identically, moved to scalar registers
+// word by word (v_readfirstlane).  Used for descriptors loaded from memory, so
+// that their fields do not occupy vector registers.
+template <typename T> __device__ inline T wave_uniform(const T &v)
+{
+    static_assert(sizeof(T) % 4 == 0, "4-byte words");
+    int w[sizeof(T) / 4];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    T out = v;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
+
 // Sum of one double per thread over the block, added atomically to *dst by
 // thread 0 (vector atomic on global memory).  Every thread must call it.
 __device__ inline void block_sum_atomic(double x, double *dst)
@@ -367,7 +382,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
             si[v] = R(0);
         }
         const V *lv = reinterpret_cast<const V *>(lds);
-        for (int j = 0; j < a.h; ++j) {
+        auto step = [&](int j) {
             const uint32_t m = 1u << (a.L + j);
             if (VE == 2 && m == 1u) {
                 sr[0] += self.v[VE - 1].x;
@@ -382,6 +397,13 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                     si[v] += nb.v[v].y;
                 }
             }
+        };
+        if constexpr (VE == 2) {
+            // kept rolled: unrolling a known h hoists every LDS read and spills
+#pragma unroll 1
+            for (int j = 0; j < a.h; ++j) step(j);
+        } else {
+            for (int j = 0; j < a.h; ++j) step(j);
         }
     };
     // Diagonal of element ee (global index idx): loaded from d (after the

@@ -81,3 +81,20 @@ def test_schedule_shape(P):
     assert len(S) == 1 + (K - 1) * (P - 1) + (P - 1)  # passes per term drop from P to P - 1
     fused = S[S[:, 0] == 2]
     assert set(fused[:, 1]) <= {0, P - 1}           # fusion happens on the end orientations
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 8, 31])
+def test_batched_step_rule_matches_schedule(K):
+    """The batched kernel derives each pass from (step j, K): j = 0 starts
+    term K-1 in the low orientation, 1 <= j < K is a fused pass completing
+    term K-j in orientation j mod 2, j = K is the final add; this must be the
+    two-orientation schedule."""
+    S = schedule(K, 2)
+    assert len(S) == K + 1
+    for j, (mode, o, k, fin) in enumerate(S):
+        if j == 0:
+            assert (mode, o, k) == (0, 0, K - 1)
+        elif j == K:
+            assert (mode, o, k, fin) == (1, j & 1, 0, 1)
+        else:
+            assert (mode, o, k, fin) == (2, j & 1, K - j, 0)
