@@ -20,6 +20,11 @@ quantum annealing":
   O2 ``cf_real`` / ``cf_coeffs``  Caratheodory-Fejer correction (sec. II.C,
                              Eq. iter) applied to the cos and sin parts.
   O3 ``closed_form_*``       the gamma = 0 and H_P = 0 closed forms.
+  O5 ``horner``              Horner's rule for a polynomial in the monomial basis
+                             (Alg. 1), with ``clenshaw`` the evaluation of a
+                             caller's Chebyshev series; ``sincos_*_coeffs`` give
+                             the sin + cos test function of Figs. 1 and 3 in both
+                             bases.
   O4 ``anneal_energy_grad``  energy of a piecewise-constant anneal and its
                              gradient by the adjoint of the Clenshaw recurrence
                              (not in the paper; derived from Eq. recursion).
@@ -247,6 +252,43 @@ def clenshaw(n: int, c: np.ndarray, d: np.ndarray, g: float, v: np.ndarray,
     lib.orc_clenshaw_final(n, _p(d), float(g), float(c[0].real), float(c[0].imag),
                            _p(v), _p(b1), _p(b2), _p(y))
     return y
+
+
+def horner(n: int, a: np.ndarray, d: np.ndarray, g: float, v: np.ndarray) -> np.ndarray:
+    """y = sum_k a_k H^k v for H = diag(d) + g sum_j X_j by Horner's rule (Alg. 1):
+    start from a_K v, then K times y <- H y + a_k v for k = K-1 .. 0."""
+    a = np.asarray(a, dtype=np.complex128)
+    v = np.ascontiguousarray(v, dtype=np.complex128)
+    K = len(a) - 1
+    y = a[K] * v
+    for k in range(K - 1, -1, -1):
+        y = hmatvec(n, d, g, y) + a[k] * v
+    return y
+
+
+def sincos_taylor_coeffs(s: float, K: int) -> np.ndarray:
+    """Maclaurin coefficients of sin(s x) + cos(s x) up to x^K (the test function
+    of Fig. 1 and Fig. 3): a_m = s^m / m! with sign + for m = 0, 1 (mod 4) and
+    - for m = 2, 3 (mod 4)."""
+    out = np.empty(K + 1)
+    term = 1.0
+    for m in range(K + 1):
+        if m > 0:
+            term *= s / m
+        out[m] = term if (m % 4) in (0, 1) else -term
+    return out
+
+
+def sincos_cheb_coeffs(s: float, K: int) -> np.ndarray:
+    """Chebyshev coefficients of sin(s x) + cos(s x) on [-1, 1] up to T_K, from the
+    Jacobi-Anger expansions (sec. II.B.1): cos(s x) = J_0(s) + 2 sum_{q>=1}
+    (-1)^q J_2q(s) T_2q(x) and sin(s x) = 2 sum_{q>=0} (-1)^q J_2q+1(s) T_2q+1(x)."""
+    Jm = _bessel_table(float(s), extra=K + 1)[:K + 1]
+    out = np.empty(K + 1)
+    for m in range(K + 1):
+        q = m // 2
+        out[m] = (1.0 if m == 0 else 2.0) * (-1.0) ** q * Jm[m]
+    return out
 
 
 def evaluation_error_bound(norms: list, n: int, u: float) -> float:

@@ -453,3 +453,82 @@ def test_pins_catch_a_wrong_time_sign(oracle_mod, monkeypatch):
     psi = synth.plus_state(n)
     y = oracle_mod.expm_action(n, E, 1.0, 1.0, psi, 1e-12)
     assert rel(y, oracle_mod.expm_action_dense(n, E, 1.0, 1.0, psi)) > 1e-3
+
+
+# ---------------------------------------------------------------- O5: caller polynomials, Horner (Alg. 1)
+
+def test_horner_vs_dense_matrix_powers(oracle_mod):
+    """Horner's rule against sum_m a_m H^m v with H the dense Kronecker-built
+    Hamiltonian and numpy matrix powers."""
+    n = 4
+    rng = np.random.default_rng(11)
+    d = rng.uniform(-1, 1, 1 << n)
+    a = rng.standard_normal(7) + 1j * rng.standard_normal(7)
+    v = synth.random_state(n, 12)
+    H = oracle_mod.hamiltonian_dense(n, d, 0.21)
+    ref = sum(a[m] * (np.linalg.matrix_power(H, m) @ v) for m in range(len(a)))
+    assert rel(oracle_mod.horner(n, a, d, 0.21, v), ref) < 1e-13
+
+
+def test_horner_gamma_zero_is_elementwise_polyval(oracle_mod):
+    """gamma = 0: p(H) v = p(d) .* v (numpy polyval)."""
+    n = 7
+    rng = np.random.default_rng(13)
+    d = rng.uniform(-1, 1, 1 << n)
+    a = rng.standard_normal(12)
+    v = synth.random_state(n, 14)
+    ref = np.polynomial.polynomial.polyval(d, a) * v
+    assert rel(oracle_mod.horner(n, a, d, 0.0, v), ref) < 1e-14
+
+
+def test_horner_matches_clenshaw_after_basis_change(oracle_mod):
+    """A degree-20 monomial polynomial (the Fig. 4 workload, smaller degree)
+    evaluated by Horner's rule and, converted to the Chebyshev basis with
+    numpy's poly2cheb, by the Clenshaw recurrence: two algorithms, one result."""
+    n = 6
+    h, J = synth.sk_instance(n, 15)
+    E = oracle_mod.energies(n, h, J)
+    c, r = oracle_mod.spectral_shift_radius(E, n, 0.7)
+    d = (E - c) / r
+    g = 0.7 / r
+    a = np.random.default_rng(16).standard_normal(21)
+    v = synth.random_state(n, 17)
+    yh = oracle_mod.horner(n, a, d, g, v)
+    yc = oracle_mod.clenshaw(n, np.polynomial.chebyshev.poly2cheb(a).astype(np.complex128), d, g, v)
+    assert rel(yh, yc) < 1e-12
+
+
+@pytest.mark.parametrize("s", [0.5, 3.0, 12.0])
+def test_sincos_taylor_coefficients(oracle_mod, s):
+    K = int(3 * s + 40)
+    x = np.linspace(-1, 1, 201)
+    p = np.polynomial.polynomial.polyval(x, oracle_mod.sincos_taylor_coeffs(s, K))
+    assert np.max(np.abs(p - (np.sin(s * x) + np.cos(s * x)))) < 1e-12 * max(1.0, np.exp(s) / 1e3)
+
+
+@pytest.mark.parametrize("s", [0.5, 3.0, 30.0, 120.0])
+def test_sincos_chebyshev_coefficients(oracle_mod, s):
+    K = int(s + 12 * s ** (1 / 3) + 30)
+    x = np.linspace(-1, 1, 401)
+    p = np.polynomial.chebyshev.chebval(x, oracle_mod.sincos_cheb_coeffs(s, K))
+    assert np.max(np.abs(p - (np.sin(s * x) + np.cos(s * x)))) < 1e-13
+
+
+def test_pins_catch_a_shifted_horner_coefficient(oracle_mod, monkeypatch):
+    """Plant y <- H y + a_{k+1} v (an off-by-one in Alg. 1): the dense pin fails."""
+    def broken(n, a, d, g, v):
+        a = np.asarray(a, dtype=np.complex128)
+        y = a[-1] * v
+        for k in range(len(a) - 2, -1, -1):
+            y = oracle_mod.hmatvec(n, d, g, y) + a[k + 1] * v
+        return y
+
+    monkeypatch.setattr(oracle_mod, "horner", broken)
+    n = 4
+    rng = np.random.default_rng(11)
+    d = rng.uniform(-1, 1, 1 << n)
+    a = rng.standard_normal(7) + 1j * rng.standard_normal(7)
+    v = synth.random_state(n, 12)
+    H = oracle_mod.hamiltonian_dense(n, d, 0.21)
+    ref = sum(a[m] * (np.linalg.matrix_power(H, m) @ v) for m in range(len(a)))
+    assert rel(oracle_mod.horner(n, a, d, 0.21, v), ref) > 1e-3
