@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-config2", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-poly", action="store_true")
     ap.add_argument("--n32", action="store_true", help="also time the 32-qubit on-the-fly workload (~1 min)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM counters)")
@@ -99,6 +100,80 @@ def config2_leg(torch, qw, synth):
                      "trunc_bound": info["trunc_bound"]}
         del psi, o, ws
     torch.cuda.empty_cache()
+    return out
+
+
+def _sincos_taylor(s, K):
+    out, term = [], 1.0
+    for m in range(K + 1):
+        if m > 0:
+            term *= s / m
+        out.append(term if m % 4 in (0, 1) else -term)
+    return out
+
+
+def _sincos_cheb(qw, np, s, K):
+    Jm = qw.bessel_j(s, K)
+    q = np.arange(K + 1) // 2
+    return np.where(np.arange(K + 1) == 0, 1.0, 2.0) * (-1.0) ** q * Jm
+
+
+def poly_leg(torch, qw, synth, np):
+    """Caller polynomials.  (1) A degree-50 polynomial with standard-normal
+    monomial coefficients on SK instances of 24 and 28 qubits (complex64, H~
+    normalised by the spectral bound): Horner's rule (Alg. 1) against the
+    Clenshaw recurrence on the same polynomial converted to the Chebyshev basis
+    (the setting of Fig. 4).  (2) (sin + cos)(s H~) psi on 100 five-qubit SK
+    instances in complex64, Chebyshev/Clenshaw against Taylor/Horner, relative
+    error against the dense eigendecomposition (the setting of Fig. 3)."""
+    out = {"degree50": {}, "sincos_n5": {}}
+    a = np.random.default_rng(0).standard_normal(51)
+    cheb = np.polynomial.chebyshev.poly2cheb(a)
+    for n in (24, 28):
+        h, J = synth.sk_instance(n, 0)
+        psi = synth.plus_state_torch(n, "cuda", torch.complex64)
+        o = torch.empty_like(psi)
+        ws = qw.Workspace.for_problem(n, 64)
+        row = {}
+        for name, coef, basis in (("horner", a, "mono"), ("clenshaw", cheb, "cheb")):
+            qw.poly_action(psi, coef, 1.0, basis=basis, h=h, J=J, out=o, workspace=ws)
+            ms = []
+            for _ in range(3):
+                _, info = qw.poly_action(psi, coef, 1.0, basis=basis, h=h, J=J, out=o, workspace=ws, timing=1)
+                ms.append(info["loop_ms"])
+            lm = float(np.median(ms))
+            row[name] = {"loop_ms": lm, "amp_terms_per_s": (1 << n) * 50 / (lm * 1e-3)}
+        row["clenshaw_over_horner_time"] = row["clenshaw"]["loop_ms"] / row["horner"]["loop_ms"]
+        out["degree50"][f"n{n}"] = row
+        del psi, o, ws
+        torch.cuda.empty_cache()
+    # (2) dense reference on 5 qubits
+    n = 5
+    N = 1 << n
+    X = np.array([[0.0, 1.0], [1.0, 0.0]])
+    F = sum(np.kron(np.kron(np.eye(1 << (n - 1 - j)), X), np.eye(1 << j)) for j in range(n))
+    idx = np.arange(N)
+    spins = 1 - 2 * ((idx[:, None] >> np.arange(n)) & 1)
+    iu = np.triu_indices(n, 1)
+    for s in (1.0, 2.0, 4.0, 8.0, 16.0, 32.0):
+        Kc, Kt = int(s + 12 * s ** (1 / 3) + 20), int(3 * s + 40)
+        cc, ct = _sincos_cheb(qw, np, s, Kc), _sincos_taylor(s, Kt)
+        ec, et = [], []
+        for seed in range(100):
+            h, J = synth.sk_instance(n, 3000 + seed)
+            E = spins @ h + (spins[:, iu[0]] * spins[:, iu[1]]) @ J
+            psi = torch.as_tensor(synth.random_state(n, 3100 + seed)).to(torch.complex64).cuda()
+            yc, info = qw.poly_action(psi, cc, 1.0, basis="cheb", h=h, J=J)
+            yt, _ = qw.poly_action(psi, ct, 1.0, basis="mono", h=h, J=J)
+            c, r = info["shift_c"], info["radius_r"]
+            lam, Q = np.linalg.eigh(np.diag((E - c) / r) + F / r)
+            v = psi.cpu().numpy().astype(np.complex128)
+            ex = Q @ ((np.sin(s * lam) + np.cos(s * lam)) * (Q.T @ v))
+            nrm = np.linalg.norm(ex)
+            ec.append(np.linalg.norm(yc.cpu().numpy() - ex) / nrm)
+            et.append(np.linalg.norm(yt.cpu().numpy() - ex) / nrm)
+        out["sincos_n5"][f"s={s:g}"] = {"K_cheb": Kc, "K_taylor": Kt, "median_err_clenshaw_c64": float(np.median(ec)),
+                                        "median_err_horner_taylor_c64": float(np.median(et))}
     return out
 
 
@@ -307,6 +382,9 @@ def main():
     if not args.no_grad:
         log("[bench] gradient: n=20, 16 segments")
         result["grad"] = grad_leg(torch, qw, synth, np)
+    if not args.no_poly:
+        log("[bench] caller polynomials: degree 50 Horner vs Clenshaw; sin+cos error vs radius")
+        result["poly"] = poly_leg(torch, qw, synth, np)
     if args.n32:
         log("[bench] n=32 on-the-fly diagonal")
         result["n32"] = n32_leg(torch, qw, synth)

@@ -70,6 +70,40 @@ typedef struct {
     double out_norm;    /* out (monitor): ||psi_out||                             */
 } qw_info;
 
+/* ------------------------------------------------------------------------
+ * Caller-supplied polynomials p(H~) psi, H~ = (H - c I) / r
+ * ------------------------------------------------------------------------ */
+typedef enum {
+    QW_BASIS_CHEB = 0, /* p(x) = sum_k coef_k T_k(x), Clenshaw's recurrence (Alg. 2)  */
+    QW_BASIS_MONO = 1  /* p(x) = sum_k coef_k x^k, Horner's rule (Alg. 1)             */
+} qw_basis;
+
+#define QW_POLY_KMAX 131072
+
+/* psi_out = p(H~) psi_in for H = diag(E) + gamma sum_j X_j (section II.B, Alg. 1
+ * and Alg. 2 with a caller-supplied polynomial; the Chebyshev case is the
+ * evaluation of Eq. recursion with arbitrary coefficients).
+ *   coef : host, 2 (K + 1) doubles, complex coefficients as (re, im) pairs,
+ *          0 <= K <= QW_POLY_KMAX;
+ *   c, r : shift and scale of H~.  r > 0 uses them as given (no spectral bound
+ *          is computed, no read-back); r <= 0 computes the bound of
+ *          qw_spectral_bound_* (c ignored), so that H~ has its spectrum in
+ *          [-1, 1]; info->shift_c and info->radius_r report the pair used.  If
+ *          the computed r is 0 the result is p(0) psi_in.
+ * Everything else as qw_expm_action_*: same layouts, workspace
+ * (qw_workspace_bytes), stream semantics, aliasing of psi_out and psi_in, and
+ * the same pass kernels (Horner's rule runs the fused pass schedule with unit
+ * scale and no b_{k+2} term).  No global phase is applied; info->monitor must be
+ * 0 (QW_EINVAL otherwise).  Complex64: gamma / r is rounded to float. */
+qw_status qw_poly_action_c64(int n, const float *diag, const double *h, const double *J, double gamma,
+                             double c, double r, const double *coef, int K, qw_basis basis,
+                             const void *psi_in, void *psi_out, void *workspace, size_t ws_bytes,
+                             void *stream, qw_info *info);
+qw_status qw_poly_action_c128(int n, const double *diag, const double *h, const double *J, double gamma,
+                              double c, double r, const double *coef, int K, qw_basis basis,
+                              const void *psi_in, void *psi_out, void *workspace, size_t ws_bytes,
+                              void *stream, qw_info *info);
+
 /* Chebyshev coefficients of exp(-i a x) on [-1, 1] (section II.B.1, Eq. cheb,
  * with a -> -a; section II.C for QW_CF).  Host only.
  *   alpha : host, kmax+1 doubles; receives alpha_0..alpha_K with

@@ -68,6 +68,9 @@ def _declare(lib):
     for name in ("qw_expm_action_c64_bounded", "qw_expm_action_c128_bounded"):
         f = getattr(lib, name)
         f.argtypes = [_i, _vp, _dp, _dp, _d, _d, _d, _d, _vp, _vp, _d, _i, _vp, _sz, _vp, ctypes.POINTER(QwInfo)]
+    for name in ("qw_poly_action_c64", "qw_poly_action_c128"):
+        f = getattr(lib, name)
+        f.argtypes = [_i, _vp, _dp, _dp, _d, _d, _d, _dp, _i, _i, _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(QwInfo)]
     lib.qw_debug_check_plan.argtypes = [_i, _i]
     lib.qw_debug_check_plan.restype = _i
     return lib
@@ -238,6 +241,63 @@ def expm_action(psi, gamma: float, t: float, *, diag=None, h=None, J=None, tol: 
         _check(fn(int(n), dptr, hp, Jp, float(gamma), float(t), float(bound[0]), float(bound[1]),
                   _vp(psi.data_ptr()), _vp(out.data_ptr()), float(tol), _METHODS[method], _vp(workspace.ptr()),
                   workspace.nbytes, _stream_ptr(stream), ctypes.byref(info)))
+    return out, info.as_dict()
+
+
+QW_BASIS_CHEB, QW_BASIS_MONO = 0, 1
+_BASES = {"cheb": QW_BASIS_CHEB, "chebyshev": QW_BASIS_CHEB, "mono": QW_BASIS_MONO, "monomial": QW_BASIS_MONO}
+
+
+def poly_action(psi, coef, gamma: float, *, basis: str = "cheb", diag=None, h=None, J=None,
+                shift: float | None = None, radius: float | None = None, out=None,
+                workspace: Workspace | None = None, stream=None, timing: int = 0):
+    """psi_out = p(H~) psi with H~ = (H - shift) / radius, H = diag(E) + gamma sum_j X_j.
+
+    coef: K + 1 (complex) coefficients, of T_k (basis "cheb": Clenshaw, Alg. 2)
+    or of x^k (basis "mono": Horner's rule, Alg. 1).  shift and radius default
+    to the spectral bound (spectrum of H~ in [-1, 1]); info["shift_c"] and
+    info["radius_r"] report the pair used.  Same state/diagonal conventions as
+    expm_action.  Returns (psi_out, info dict)."""
+    torch = _torch()
+    if not (psi.is_cuda and psi.is_contiguous() and psi.dim() == 1):
+        raise ValueError("psi must be a contiguous 1-D CUDA tensor")
+    N = psi.numel()
+    n = N.bit_length() - 1
+    if N != (1 << n):
+        raise ValueError("len(psi) must be a power of two")
+    prec = _prec_of(psi)
+    cf = np.asarray(coef, dtype=np.complex128).ravel()
+    if cf.size < 1:
+        raise ValueError("need at least one coefficient")
+    cpair = np.ascontiguousarray(np.stack([cf.real, cf.imag], axis=1).ravel())
+    if out is None:
+        out = torch.empty_like(psi)
+    elif out.dtype != psi.dtype or out.numel() != N or not out.is_contiguous():
+        raise ValueError("out must match psi")
+    if diag is not None:
+        want = torch.float32 if prec == 64 else torch.float64
+        if diag.dtype != want or not diag.is_contiguous() or diag.numel() != N or not diag.is_cuda:
+            raise ValueError("diag must be a contiguous CUDA vector of 2^n energies in the state's real precision")
+        hp = Jp = None
+    else:
+        if h is None or J is None:
+            raise ValueError("give diag, or h and J")
+        _h, hp = _host_f64(h, n)
+        _J, Jp = _host_f64(J, n * (n - 1) // 2)
+    otf = diag is None and n >= 31
+    if workspace is None:
+        workspace = Workspace.for_problem(n, prec, otf, device=psi.device)
+    c = 0.0 if shift is None else float(shift)
+    r = 0.0 if radius is None else float(radius)
+    if (shift is None) != (radius is None):
+        raise ValueError("give both shift and radius, or neither")
+    info = QwInfo()
+    info.timing = int(timing)
+    dptr = _vp(diag.data_ptr()) if diag is not None else None
+    fn = lib().qw_poly_action_c64 if prec == 64 else lib().qw_poly_action_c128
+    _check(fn(int(n), dptr, hp, Jp, float(gamma), c, r, cpair.ctypes.data_as(_dp), int(cf.size - 1),
+              _BASES[basis], _vp(psi.data_ptr()), _vp(out.data_ptr()), _vp(workspace.ptr()), workspace.nbytes,
+              _stream_ptr(stream), ctypes.byref(info)))
     return out, info.as_dict()
 
 

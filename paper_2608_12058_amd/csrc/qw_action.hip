@@ -322,10 +322,20 @@ struct PassTimer {
     }
 };
 
+// Caller-supplied polynomial: p(x) = sum_k coef_k T_k(x) (Chebyshev basis,
+// Clenshaw) or sum_k coef_k x^k (monomial basis, Horner's rule), complex
+// coefficients as (re, im) pairs.
+struct PolyIn {
+    const double *coef;
+    int K;
+    int horner;
+};
+
 template <typename R>
 static qw_status action_impl(int n, const R *diag, const double *h, const double *J, double gamma, double t,
                              const void *psi_in, void *psi_out, double tol, int method, void *workspace,
-                             size_t ws_bytes, void *stream, qw_info *info, const double *given_cr = nullptr)
+                             size_t ws_bytes, void *stream, qw_info *info, const double *given_cr = nullptr,
+                             const PolyIn *poly = nullptr)
 {
     using C = typename Cplx<R>::T;
     using V = CVec<R>;
@@ -346,7 +356,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
 
     EnergyTables T{};
     double c = 0.0, r = 0.0;
-    const bool monitor = (info && info->monitor) || given_cr;
+    if (poly && info && info->monitor) { set_error("the norm monitor applies to exp(-itH) only"); return QW_EINVAL; }
+    const bool monitor = !poly && ((info && info->monitor) || given_cr);
     if (given_cr) {
         c = given_cr[0];
         r = given_cr[1];
@@ -363,14 +374,14 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     // g = gamma / r; in single precision round g towards zero and take
     // r = gamma / g, which is still a bound and makes g exact in float.
     double g = (r > 0.0) ? gamma / r : 0.0;
-    if (sizeof(R) == 4 && gamma != 0.0 && r > 0.0) {
+    if (sizeof(R) == 4 && gamma != 0.0 && r > 0.0 && !poly) {
         float gf = (float)g;
         if (std::fabs((double)gf) > std::fabs(g)) gf = std::nextafter(gf, 0.0f);
         g = (double)gf;
         r = gamma / g;
     }
     const double inv_r = (r > 0.0) ? 1.0 / r : 0.0;
-    const double ph_r = std::cos(t * c), ph_i = -std::sin(t * c);   // exp(-i t c)
+    const double ph_r = poly ? 1.0 : std::cos(t * c), ph_i = poly ? 0.0 : -std::sin(t * c);   // exp(-i t c)
     const uint64_t nvec = N / V::N;
     const int eg = grid_for(nvec, 256 * 4, 1 << 16);
 
@@ -387,9 +398,20 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     const C *psi = static_cast<const C *>(psi_in);
     C *out = static_cast<C *>(psi_out);
     if (r == 0.0) {
+        // H = c I: exp(-itH) psi = exp(-itc) psi; a caller's polynomial is taken at H~ = 0
+        double sr = ph_r, si = ph_i;
+        if (poly) {
+            sr = si = 0.0;
+            for (int k = 0; k <= poly->K; ++k) {
+                const double tk = poly->horner ? (k == 0 ? 1.0 : 0.0)
+                                               : ((k & 1) ? 0.0 : ((k & 2) ? -1.0 : 1.0));   // T_k(0)
+                sr += tk * poly->coef[2 * k];
+                si += tk * poly->coef[2 * k + 1];
+            }
+        }
         timer.mark(1);
         hipLaunchKernelGGL(k_scale<R>, dim3(eg), dim3(256), 0, s, reinterpret_cast<const V *>(psi),
-                           reinterpret_cast<V *>(out), (R)ph_r, (R)ph_i, nvec);
+                           reinterpret_cast<V *>(out), (R)sr, (R)si, nvec);
         QW_HIP(hipGetLastError());
         return timer.finish(info);
     }
@@ -408,15 +430,27 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     }
     QW_HIP(hipGetLastError());
 
-    // coefficients (host, double)
-    const double a = t * r;
+    // coefficients (host, double): c_k = (-i)^k alpha_k, or the caller's
+    const double a = poly ? 0.0 : t * r;
     std::vector<double> alpha;
     int K = 0;
     double err = 0.0;
-    if (coefficients(a, tol, method, alpha, &K, &err) != 0) {
+    if (poly) {
+        K = poly->K;
+    } else if (coefficients(a, tol, method, alpha, &K, &err) != 0) {
         set_error("coefficient setup failed");
         return QW_ENOCONV;
     }
+    std::vector<double> cre(K + 1), cim(K + 1);
+    for (int k = 0; k <= K; ++k) {
+        if (poly) {
+            cre[k] = poly->coef[2 * k];
+            cim[k] = poly->coef[2 * k + 1];
+        } else {
+            coef_of(alpha, k, cre[k], cim[k]);
+        }
+    }
+    const bool horner = poly && poly->horner;
     const std::vector<PassPlan> plan = plan_passes<R>(n);
     if (info) {
         info->K = K;
@@ -430,13 +464,15 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         if (K > KMAX_ONCHIP) { set_error("degree too large for the on-chip path"); return QW_ENOMEM; }
         std::vector<C> ch(K + 1);
         for (int k = 0; k <= K; ++k) {
-            double cr, ci;
-            coef_of(alpha, k, cr, ci);
-            ch[k].x = (R)cr;
-            ch[k].y = (R)ci;
+            ch[k].x = (R)cre[k];
+            ch[k].y = (R)cim[k];
         }
         C *dcoef = reinterpret_cast<C *>(ws + L.coef);
         OnchipItem<R> item{psi, out, dn, dcoef, (R)g, (R)ph_r, (R)ph_i, n, K};
+        if (horner) {
+            item.two = R(1);
+            item.sub = R(0);
+        }
         OnchipItem<R> *ditem = reinterpret_cast<OnchipItem<R> *>(ws + L.items);
         QW_HIP(hipMemcpyAsync(dcoef, ch.data(), ch.size() * sizeof(C), hipMemcpyHostToDevice, s));
         QW_HIP(hipMemcpyAsync(ditem, &item, sizeof(item), hipMemcpyHostToDevice, s));
@@ -449,8 +485,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     }
 
     if (K == 0) {
-        double cr, ci;
-        coef_of(alpha, 0, cr, ci);
+        const double cr = cre[0], ci = cim[0];
         const double pr = cr * ph_r - ci * ph_i, pi = cr * ph_i + ci * ph_r;
         timer.mark(1);
         hipLaunchKernelGGL(k_scale<R>, dim3(eg), dim3(256), 0, s, reinterpret_cast<const V *>(psi),
@@ -477,8 +512,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     timer.mark(1);
     {
         // b_K = c_K psi (b_{K+1} = 0 is never read: the first pass takes acc = NULL)
-        double cr, ci;
-        coef_of(alpha, K, cr, ci);
+        const double cr = cre[K], ci = cim[K];
         hipLaunchKernelGGL(k_scale<R>, dim3(eg), dim3(256), 0, s, reinterpret_cast<const V *>(psi),
                            reinterpret_cast<V *>(X), (R)cr, (R)ci, nvec);
         QW_HIP(hipGetLastError());
@@ -494,7 +528,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     const std::vector<SchedPass> sched = fused_schedule(K, P);
     PassTimer ptimer(info && info->timing == 2, s, sched.size() + 1);
     ptimer.mark(-1);
-    auto scale_of = [](int k) { return k == 0 ? R(1) : R(2); };
+    auto scale_of = [horner](int k) { return (k == 0 || horner) ? R(1) : R(2); };
+    pa.sub = horner ? R(0) : R(1);
     for (const SchedPass &sp : sched) {
         const PassPlan &pl = plan[sp.orient];
         double cr = 0.0, ci = 0.0;
@@ -508,8 +543,9 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         pa.dst2 = nullptr;
         pa.norm_acc = nullptr;
         if (sp.mode == PM_START) {
-            coef_of(alpha, sp.k, cr, ci);
-            pa.acc = (sp.k == K - 1) ? nullptr : Y;
+            cr = cre[sp.k];
+            ci = cim[sp.k];
+            pa.acc = (sp.k == K - 1 || horner) ? nullptr : Y;
             pa.dst = sp.fin ? out : Y;
             pa.scale = scale_of(sp.k);
             if (sp.fin) { pa.pr = (R)ph_r; pa.pi = (R)ph_i; }
@@ -524,7 +560,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
                 if (monitor) pa.norm_acc = norms;
             }
         } else {
-            coef_of(alpha, sp.k - 1, cr, ci);
+            cr = cre[sp.k - 1];
+            ci = cim[sp.k - 1];
             pa.acc = Y;
             pa.dst = Y;
             pa.dst2 = X;
@@ -594,6 +631,22 @@ int check_plan(int n, int prec)
     return covered_bits == n ? (int)plan.size() : -6;
 }
 
+template <typename R>
+static qw_status poly_entry(int n, const R *diag, const double *h, const double *J, double gamma, double c, double r,
+                            const double *coef, int K, qw_basis basis, const void *psi_in, void *psi_out,
+                            void *workspace, size_t ws_bytes, void *stream, qw_info *info)
+{
+    if (basis != QW_BASIS_CHEB && basis != QW_BASIS_MONO) { set_error("unknown basis"); return QW_EINVAL; }
+    if (K < 0 || K > QW_POLY_KMAX || !coef) { set_error("need coef with K + 1 entries, 0 <= K <= QW_POLY_KMAX"); return QW_EINVAL; }
+    for (int k = 0; k < 2 * (K + 1); ++k)
+        if (!finite(coef[k])) { set_error("coef has a non-finite entry"); return QW_EINVAL; }
+    if (!finite(c) || !finite(r)) { set_error("c and r must be finite"); return QW_EINVAL; }
+    const PolyIn poly{coef, K, basis == QW_BASIS_MONO ? 1 : 0};
+    const double cr[2] = {c, r};
+    return action_impl<R>(n, diag, h, J, gamma, 0.0, psi_in, psi_out, 1.0, QW_CHEB, workspace, ws_bytes, stream,
+                          info, r > 0.0 ? cr : nullptr, &poly);
+}
+
 }  // namespace qw
 
 using namespace qw;
@@ -601,7 +654,7 @@ using namespace qw;
 extern "C" {
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.2 (gfx950, fused passes)"; }
+const char *qw_version(void) { return "qwexp 0.3 (gfx950, fused passes, Horner)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {
@@ -676,6 +729,22 @@ qw_status qw_expm_action_c128_bounded(int n, const double *diag, const double *h
     const double cr[2] = {c, r};
     return action_impl<double>(n, diag, h, J, gamma, t, psi_in, psi_out, tol, (int)method, workspace, ws_bytes,
                                stream, info, cr);
+}
+
+qw_status qw_poly_action_c64(int n, const float *diag, const double *h, const double *J, double gamma, double c,
+                             double r, const double *coef, int K, qw_basis basis, const void *psi_in, void *psi_out,
+                             void *workspace, size_t ws_bytes, void *stream, qw_info *info)
+{
+    return poly_entry<float>(n, diag, h, J, gamma, c, r, coef, K, basis, psi_in, psi_out, workspace, ws_bytes, stream,
+                             info);
+}
+
+qw_status qw_poly_action_c128(int n, const double *diag, const double *h, const double *J, double gamma, double c,
+                              double r, const double *coef, int K, qw_basis basis, const void *psi_in, void *psi_out,
+                              void *workspace, size_t ws_bytes, void *stream, qw_info *info)
+{
+    return poly_entry<double>(n, diag, h, J, gamma, c, r, coef, K, basis, psi_in, psi_out, workspace, ws_bytes,
+                              stream, info);
 }
 
 // Host-only: the pass sequence for degree K and P orientations as (mode,

@@ -254,6 +254,7 @@ template <typename R> struct PassArgs {
     R scale2;      // FUSED: the same for b_{k-1}
     R cr, ci;      // START: c_k;  FUSED: c_{k-1}
     R pr, pi;      // START, ADD: multiplier of the result (the global phase on the last pass)
+    R sub = R(1);  // START, FUSED: weight of the subtracted b_{k+2} (Clenshaw 1, Horner 0)
     int n, L, g0, h;
     double *norm_acc = nullptr;   // if set: += sum |b|^2 of the completed vector (atomic, one per block)
 };
@@ -320,10 +321,12 @@ __global__ void k_qtable_orient(const double *hJ, int n, int L, int g0, int h, d
 
 // One pass over one tile (see tile_base/tile_index); F_group sums the flips of
 // the tile's h group bits:
-//  START: dst = scale (d .* b1 + g F b1) - acc + c_k psi,            then *= (pr + i pi)
+//  START: dst = scale (d .* b1 + g F b1) - sub acc + c_k psi,        then *= (pr + i pi)
 //  ADD:   dst = acc + scale g F b1,                                   then *= (pr + i pi)
 //  FUSED: b_k = acc + scale g F b1 (completes term k) -> dst;
-//         dst2 = scale2 (d .* b_k + g F b_k) - b1 + c_{k-1} psi (first part of term k-1)
+//         dst2 = scale2 (d .* b_k + g F b_k) - sub b1 + c_{k-1} psi (first part of term k-1)
+// The Clenshaw recurrence uses scale 2 (1 on the final step) and sub 1; Horner's
+// rule (y_k = H y_{k+1} + a_k psi) the same passes with scale 1 and sub 0.
 // FUSED needs b_k of the whole tile, so the tile is re-staged through LDS.
 template <typename R, int TB, int NT, int MODE, bool OTF>
 __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, typename Cplx<R>::T *lds)
@@ -460,8 +463,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                     const C bk = accv[q].v[v], bp = own[q].v[v], ps = psiv[q].v[v];
                     const R hr = dd * bk.x + a.g * sr[v];
                     const R hi = dd * bk.y + a.g * si[v];
-                    out.v[v].x = (a.scale2 * hr - bp.x) + (a.cr * ps.x - a.ci * ps.y);
-                    out.v[v].y = (a.scale2 * hi - bp.y) + (a.cr * ps.y + a.ci * ps.x);
+                    out.v[v].x = (a.scale2 * hr - a.sub * bp.x) + (a.cr * ps.x - a.ci * ps.y);
+                    out.v[v].y = (a.scale2 * hi - a.sub * bp.y) + (a.cr * ps.y + a.ci * ps.x);
                     if (a.norm_acc) nrm += (double)bk.x * bk.x + (double)bk.y * bk.y;
                 }
                 *reinterpret_cast<V *>(a.dst + idx) = accv[q];
@@ -487,8 +490,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                         const C b = own[q].v[v], ac = accv[q].v[v], ps = psiv[q].v[v];
                         const R hr = dd * b.x + a.g * sr;
                         const R hi = dd * b.y + a.g * si;
-                        o.x = (a.scale * hr - ac.x) + (a.cr * ps.x - a.ci * ps.y);
-                        o.y = (a.scale * hi - ac.y) + (a.cr * ps.y + a.ci * ps.x);
+                        o.x = (a.scale * hr - a.sub * ac.x) + (a.cr * ps.x - a.ci * ps.y);
+                        o.y = (a.scale * hi - a.sub * ac.y) + (a.cr * ps.y + a.ci * ps.x);
                     } else {
                         const C ac = accv[q].v[v];
                         const R sg = a.scale * a.g;
@@ -525,6 +528,7 @@ template <typename R> struct OnchipItem {
     R g;
     R pr, pi;       // global phase
     int n, K;
+    R two = R(2), sub = R(1);   // Clenshaw (2, 1); Horner's rule (1, 0)
 };
 
 template <typename R, int TB, int NT>
@@ -569,8 +573,8 @@ __global__ void __launch_bounds__(NT) k_onchip(const OnchipItem<R> *items, const
                     }
                     const R hr = dd[q] * b1[q].x + I.g * sr;
                     const R hi = dd[q] * b1[q].y + I.g * si;
-                    nb[q].x = (R(2) * hr - b2[q].x) + (ck.x * ps[q].x - ck.y * ps[q].y);
-                    nb[q].y = (R(2) * hi - b2[q].y) + (ck.x * ps[q].y + ck.y * ps[q].x);
+                    nb[q].x = (I.two * hr - I.sub * b2[q].x) + (ck.x * ps[q].x - ck.y * ps[q].y);
+                    nb[q].y = (I.two * hi - I.sub * b2[q].y) + (ck.x * ps[q].y + ck.y * ps[q].x);
                 }
             }
             __syncthreads();
@@ -603,8 +607,8 @@ __global__ void __launch_bounds__(NT) k_onchip(const OnchipItem<R> *items, const
                     }
                     const R hr = dd[q] * b1[q].x + I.g * sr;
                     const R hi = dd[q] * b1[q].y + I.g * si;
-                    y.x = (hr - b2[q].x) + (c0.x * ps[q].x - c0.y * ps[q].y);
-                    y.y = (hi - b2[q].y) + (c0.x * ps[q].y + c0.y * ps[q].x);
+                    y.x = (hr - I.sub * b2[q].x) + (c0.x * ps[q].x - c0.y * ps[q].y);
+                    y.y = (hi - I.sub * b2[q].y) + (c0.x * ps[q].y + c0.y * ps[q].x);
                 }
                 C o;
                 o.x = I.pr * y.x - I.pi * y.y;
