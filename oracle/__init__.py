@@ -20,6 +20,9 @@ quantum annealing":
   O2 ``cf_real`` / ``cf_coeffs``  Caratheodory-Fejer correction (sec. II.C,
                              Eq. iter) applied to the cos and sin parts.
   O3 ``closed_form_*``       the gamma = 0 and H_P = 0 closed forms.
+  O6 ``anneal_cfet4``        fourth-order commutator-free Magnus steps for a
+                             time-dependent anneal (sec. III.B), each exponential
+                             by O1.
   O5 ``horner``              Horner's rule for a polynomial in the monomial basis
                              (Alg. 1), with ``clenshaw`` the evaluation of a
                              caller's Chebyshev series; ``sincos_*_coeffs`` give
@@ -289,6 +292,36 @@ def sincos_cheb_coeffs(s: float, K: int) -> np.ndarray:
         q = m // 2
         out[m] = (1.0 if m == 0 else 2.0) * (-1.0) ** q * Jm[m]
     return out
+
+
+def schedule_value(coef, T: float, t: float) -> float:
+    """A(t) for a schedule given by monomial coefficients in s = t / T."""
+    return float(np.polynomial.polynomial.polyval(t / T, np.asarray(coef, dtype=np.float64)))
+
+
+def anneal_cfet4(n: int, E: np.ndarray, a_coef, b_coef, T: float, step_sizes, psi: np.ndarray,
+                 tols) -> np.ndarray:
+    """U(T, 0) psi for H(t) = A(t) diag(E) + B(t) sum_j X_j by the fourth-order
+    commutator-free Magnus steps of sec. III.B: a step of length h from t uses
+    the two Gauss-Legendre nodes t + (1/2 -+ sqrt(3)/6) h and applies
+    exp(-i h (w1 H(t1) + w2 H(t2))) and then exp(-i h (w2 H(t1) + w1 H(t2))),
+    w_{1,2} = 1/4 +- sqrt(3)/6; every exponential of alpha diag(E) + beta sum X_j
+    is ``expm_action`` (O1) with the energies scaled by alpha.  ``step_sizes``
+    lists h for every step, ``tols`` the truncation tolerance of every step's
+    two exponentials."""
+    r3 = np.sqrt(3.0)
+    c1, c2 = 0.5 - r3 / 6.0, 0.5 + r3 / 6.0
+    w1, w2 = 0.25 + r3 / 6.0, 0.25 - r3 / 6.0
+    E = np.asarray(E, dtype=np.float64)
+    y = np.asarray(psi, dtype=np.complex128).copy()
+    t = 0.0
+    for hs, tol in zip(step_sizes, tols):
+        A1, A2 = schedule_value(a_coef, T, t + c1 * hs), schedule_value(a_coef, T, t + c2 * hs)
+        B1, B2 = schedule_value(b_coef, T, t + c1 * hs), schedule_value(b_coef, T, t + c2 * hs)
+        for alpha, beta in ((w1 * A1 + w2 * A2, w1 * B1 + w2 * B2), (w2 * A1 + w1 * A2, w2 * B1 + w1 * B2)):
+            y = expm_action(n, alpha * E, beta, hs, y, tol)
+        t += hs
+    return y
 
 
 def evaluation_error_bound(norms: list, n: int, u: float) -> float:
