@@ -104,6 +104,59 @@ qw_status qw_poly_action_c128(int n, const double *diag, const double *h, const 
                               const void *psi_in, void *psi_out, void *workspace, size_t ws_bytes,
                               void *stream, qw_info *info);
 
+/* ------------------------------------------------------------------------
+ * Time-dependent anneal, fourth-order commutator-free Magnus steps (sec. III.B)
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int timing;            /* in: nonzero times the call with HIP events and
+                              synchronises                                       */
+    int steps;             /* out: steps taken                                    */
+    int exponentials;      /* out: exponentials applied (two per step)            */
+    long long terms;       /* out: sum of the Chebyshev degrees over all
+                              exponentials (the matrix-vector products)          */
+    double err_bound;      /* out: sum over steps of the bound on the leading
+                              local error, b(t) h^5                              */
+    double h_min, h_max;   /* out: smallest and largest step                      */
+    double comm_bound;     /* out: the bound used for ||[H_P, sum_j X_j]||        */
+    float total_ms;        /* out (timing)                                        */
+} qw_cfet_info;
+
+/* psi_out = U(T, 0) psi_in for H(t) = A(t) H_P + B(t) sum_j X_j, H_P the Ising
+ * diagonal of (h, J), by the fourth-order commutator-free Magnus method the
+ * paper proposes for annealing (sec. III.B): each step of length h applies
+ *   exp(-i h (a1 H(t1) + a2 H(t2))) first, then exp(-i h (a2 H(t1) + a1 H(t2))),
+ * t_{1,2} = t + (1/2 -+ sqrt(3)/6) h, a_{1,2} = 1/4 +- sqrt(3)/6, each an
+ * action call of the Chebyshev path on tables prepared once.
+ *   A_coef, B_coef : host, A_deg + 1 / B_deg + 1 monomial coefficients in
+ *                    s = t / T (degrees 0..16), e.g. A = s, B = 1 - s;
+ *   steps > 0      : that many equal steps, tol the total truncation budget of
+ *                    the Chebyshev series (tol h / (2T) per exponential);
+ *   steps == 0     : adaptive steps h(t) = (tol / (2 T b(t)))^(1/4) from the
+ *                    bound b(t) on the leading local error h^5 E5 (derived by
+ *                    series expansion; it uses ||H_P - c||, n and the bound
+ *                    sum_j 2(|h_j| + sum_k |J_jk|) on ||[H_P, sum_j X_j]||), so no
+ *                    trial steps are run; half of tol goes to the series;
+ *   step_sizes     : host, may be NULL; receives the first step_cap step sizes;
+ *   workspace      : as qw_workspace_bytes(n, 64 or 128, n >= 31);
+ *   psi_out        : may alias psi_in; every exponential after the first runs
+ *                    in place on psi_out.
+ * Synchronises the stream once (the energy range).  QW_ENOCONV if more than
+ * 2^20 steps would be needed. */
+qw_status qw_anneal_cfet4_c64(int n, const double *h, const double *J, const double *A_coef, int A_deg,
+                              const double *B_coef, int B_deg, double T, int steps, double tol,
+                              const void *psi_in, void *psi_out, double *step_sizes, int step_cap,
+                              void *workspace, size_t ws_bytes, void *stream, qw_cfet_info *info);
+qw_status qw_anneal_cfet4_c128(int n, const double *h, const double *J, const double *A_coef, int A_deg,
+                               const double *B_coef, int B_deg, double T, int steps, double tol,
+                               const void *psi_in, void *psi_out, double *step_sizes, int step_cap,
+                               void *workspace, size_t ws_bytes, void *stream, qw_cfet_info *info);
+
+/* Host-only: the bound b(t) on ||E5|| used for the adaptive steps, for the
+ * energy range [emin, emax] of H_P. */
+qw_status qw_cfet4_step_bound(int n, const double *h, const double *J, const double *A_coef, int A_deg,
+                              const double *B_coef, int B_deg, double T, double emin, double emax, double t,
+                              double *bound);
+
 /* Chebyshev coefficients of exp(-i a x) on [-1, 1] (section II.B.1, Eq. cheb,
  * with a -> -a; section II.C for QW_CF).  Host only.
  *   alpha : host, kmax+1 doubles; receives alpha_0..alpha_K with

@@ -71,6 +71,11 @@ def _declare(lib):
     for name in ("qw_poly_action_c64", "qw_poly_action_c128"):
         f = getattr(lib, name)
         f.argtypes = [_i, _vp, _dp, _dp, _d, _d, _d, _dp, _i, _i, _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(QwInfo)]
+    for name in ("qw_anneal_cfet4_c64", "qw_anneal_cfet4_c128"):
+        f = getattr(lib, name)
+        f.argtypes = [_i, _dp, _dp, _dp, _i, _dp, _i, _d, _i, _d, _vp, _vp, _dp, _i, _vp, _sz, _vp,
+                      ctypes.POINTER(CfetInfo)]
+    lib.qw_cfet4_step_bound.argtypes = [_i, _dp, _dp, _dp, _i, _dp, _i, _d, _d, _d, _d, _dp]
     lib.qw_debug_check_plan.argtypes = [_i, _i]
     lib.qw_debug_check_plan.restype = _i
     return lib
@@ -299,6 +304,64 @@ def poly_action(psi, coef, gamma: float, *, basis: str = "cheb", diag=None, h=No
               _BASES[basis], _vp(psi.data_ptr()), _vp(out.data_ptr()), _vp(workspace.ptr()), workspace.nbytes,
               _stream_ptr(stream), ctypes.byref(info)))
     return out, info.as_dict()
+
+
+class CfetInfo(ctypes.Structure):
+    _fields_ = [("timing", ctypes.c_int), ("steps", ctypes.c_int), ("exponentials", ctypes.c_int),
+                ("terms", ctypes.c_longlong), ("err_bound", ctypes.c_double), ("h_min", ctypes.c_double),
+                ("h_max", ctypes.c_double), ("comm_bound", ctypes.c_double), ("total_ms", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def anneal_cfet4(psi, h, J, A, B, T: float, *, steps: int = 0, tol: float = 1e-6, out=None,
+                 workspace: Workspace | None = None, stream=None, timing: int = 0, max_record: int = 1 << 16):
+    """psi(T) for H(t) = A(t) H_P + B(t) sum_j X_j by fourth-order commutator-free
+    Magnus steps (sec. III.B).  A, B: monomial coefficients in s = t / T (e.g.
+    A = [0, 1], B = [1, -1] for a linear anneal).  steps > 0: equal steps; 0:
+    adaptive steps from the library's bound on the leading local error, with
+    tol the total error target.  Returns (psi_out, info dict, step sizes)."""
+    torch = _torch()
+    if not (psi.is_cuda and psi.is_contiguous() and psi.dim() == 1):
+        raise ValueError("psi must be a contiguous 1-D CUDA tensor")
+    N = psi.numel()
+    n = N.bit_length() - 1
+    if N != (1 << n):
+        raise ValueError("len(psi) must be a power of two")
+    prec = _prec_of(psi)
+    _h, hp = _host_f64(h, n)
+    _J, Jp = _host_f64(J, n * (n - 1) // 2)
+    a = np.ascontiguousarray(np.asarray(A, dtype=np.float64).ravel())
+    b = np.ascontiguousarray(np.asarray(B, dtype=np.float64).ravel())
+    if out is None:
+        out = torch.empty_like(psi)
+    elif out.dtype != psi.dtype or out.numel() != N or not out.is_contiguous():
+        raise ValueError("out must match psi")
+    if workspace is None:
+        workspace = Workspace.for_problem(n, prec, n >= 31, device=psi.device)
+    rec = np.zeros(max(1, int(max_record)), dtype=np.float64)
+    info = CfetInfo()
+    info.timing = int(timing)
+    fn = lib().qw_anneal_cfet4_c64 if prec == 64 else lib().qw_anneal_cfet4_c128
+    _check(fn(int(n), hp, Jp, a.ctypes.data_as(_dp), int(a.size - 1), b.ctypes.data_as(_dp), int(b.size - 1),
+              float(T), int(steps), float(tol), _vp(psi.data_ptr()), _vp(out.data_ptr()), rec.ctypes.data_as(_dp),
+              int(rec.size), _vp(workspace.ptr()), workspace.nbytes, _stream_ptr(stream), ctypes.byref(info)))
+    d = info.as_dict()
+    return out, d, rec[:min(d["steps"], rec.size)].copy()
+
+
+def cfet4_step_bound(n: int, h, J, A, B, T: float, emin: float, emax: float, t: float) -> float:
+    """Host-only: the library's bound on ||E5|| at time t (leading local error per h^5)."""
+    _h, hp = _host_f64(h, n)
+    _J, Jp = _host_f64(J, n * (n - 1) // 2)
+    a = np.ascontiguousarray(np.asarray(A, dtype=np.float64).ravel())
+    b = np.ascontiguousarray(np.asarray(B, dtype=np.float64).ravel())
+    out = _d(0.0)
+    _check(lib().qw_cfet4_step_bound(int(n), hp, Jp, a.ctypes.data_as(_dp), int(a.size - 1), b.ctypes.data_as(_dp),
+                                     int(b.size - 1), float(T), float(emin), float(emax), float(t),
+                                     ctypes.byref(out)))
+    return float(out.value)
 
 
 def debug_check_plan(n: int, precision: int) -> int:

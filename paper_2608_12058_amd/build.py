@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libqwexp.so")
 
-SOURCES = ["qw_action.hip", "qw_batched.hip", "qw_grad.hip", "qw_coeffs.cpp"]
+SOURCES = ["qw_action.hip", "qw_batched.hip", "qw_grad.hip", "qw_cfet.hip", "qw_coeffs.cpp"]
 
 # Packed fp32 instructions are disabled for all device code; the host pass of
 # hipcc warns that it does not know the feature, which is harmless.

@@ -18,6 +18,7 @@
 // coalescing) and adds that group's flips.  Small instances (n <= 13) run the
 // whole recurrence inside one workgroup with the vector resident in LDS.
 #include "qw_kernels.h"
+#include "qw_prepared.h"
 
 #include <hip/hip_runtime.h>
 
@@ -335,7 +336,7 @@ template <typename R>
 static qw_status action_impl(int n, const R *diag, const double *h, const double *J, double gamma, double t,
                              const void *psi_in, void *psi_out, double tol, int method, void *workspace,
                              size_t ws_bytes, void *stream, qw_info *info, const double *given_cr = nullptr,
-                             const PolyIn *poly = nullptr)
+                             const PolyIn *poly = nullptr, const Prepared *prep = nullptr)
 {
     using C = typename Cplx<R>::T;
     using V = CVec<R>;
@@ -357,14 +358,18 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     EnergyTables T{};
     double c = 0.0, r = 0.0;
     if (poly && info && info->monitor) { set_error("the norm monitor applies to exp(-itH) only"); return QW_EINVAL; }
-    const bool monitor = !poly && ((info && info->monitor) || given_cr);
+    const bool monitor = !poly && ((info && info->monitor) || (given_cr && !prep));
     if (given_cr) {
         c = given_cr[0];
         r = given_cr[1];
         if (!finite(c) || !(r > 0.0) || !finite(r)) { set_error("the given bound needs finite c and r > 0"); return QW_EINVAL; }
         if (!diag) {
-            st = setup_tables(n, h, J, ws, L, s, &T);
-            if (st != QW_OK) return st;
+            if (prep) {
+                T = prep->T;
+            } else {
+                st = setup_tables(n, h, J, ws, L, s, &T);
+                if (st != QW_OK) return st;
+            }
         }
     } else {
         st = bound_impl<R>(n, diag, h, J, gamma, ws, L, s, &T, &c, &r);
@@ -416,7 +421,9 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         return timer.finish(info);
     }
 
-    // normalised diagonal
+    // normalised diagonal d~ = (E' - c) / r of the energies E' = escale * E
+    const double es = prep ? prep->escale : 1.0;
+    const double norm_c = (es != 0.0) ? c / es : 0.0, norm_inv_r = es * inv_r;
     R *dn = otf ? nullptr : reinterpret_cast<R *>(ws + L.d);
     float *qt = reinterpret_cast<float *>(ws + L.qt);
     if (!otf) {
@@ -425,7 +432,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
                                diag, N, c, inv_r, dn);
         } else {
             hipLaunchKernelGGL(k_normalize_energy<R>, dim3(grid_for(N >> T.LB, 1, 1 << 16)), dim3(256), 0, s,
-                               T, c, inv_r, dn);
+                               T, norm_c, norm_inv_r, dn);
         }
     }
     QW_HIP(hipGetLastError());
@@ -507,7 +514,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     if (otf) {
         for (int o = 0; o < P; ++o)
             hipLaunchKernelGGL(k_qtable_orient<0>, dim3((1 << LB_TAB) / 256), dim3(256), 0, s, T.h, n, plan[o].L,
-                               plan[o].g0, plan[o].h, inv_r, qt + (size_t)o * (1 << LB_TAB));
+                               plan[o].g0, plan[o].h, norm_inv_r, qt + (size_t)o * (1 << LB_TAB));
     }
     timer.mark(1);
     {
@@ -521,8 +528,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     pa.psi = psi;
     pa.d = dn;
     pa.hJ = T.h;
-    pa.otf_c = c;
-    pa.otf_inv_r = inv_r;
+    pa.otf_c = norm_c;
+    pa.otf_inv_r = norm_inv_r;
     pa.g = (R)g;
     pa.n = n;
     const std::vector<SchedPass> sched = fused_schedule(K, P);
@@ -646,6 +653,54 @@ static qw_status poly_entry(int n, const R *diag, const double *h, const double 
     return action_impl<R>(n, diag, h, J, gamma, 0.0, psi_in, psi_out, 1.0, QW_CHEB, workspace, ws_bytes, stream,
                           info, r > 0.0 ? cr : nullptr, &poly);
 }
+
+template <typename R>
+qw_status prepare_energy(int n, const double *h, const double *J, void *workspace, size_t ws_bytes, void *stream,
+                         EnergyTables *T, double *emin, double *emax)
+{
+    if (n < 1 || n > 32 || !h || (n > 1 && !J) || !workspace) { set_error("bad arguments"); return QW_EINVAL; }
+    const WsLayout L = ws_layout(n, prec_of<R>(), n >= 31);
+    if (ws_bytes < L.total) {
+        set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
+        return QW_ENOMEM;
+    }
+    char *ws = static_cast<char *>(workspace);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    qw_status st = setup_tables(n, h, J, ws, L, s, T);
+    if (st != QW_OK) return st;
+    return minmax<R>(n, nullptr, T, ws, L, s, emin, emax);
+}
+
+template <typename R>
+qw_status scaled_action(int n, const double *h, const double *J, const EnergyTables &T, double alpha, double emin,
+                        double emax, double beta, double t, const void *psi_in, void *psi_out, double tol,
+                        void *workspace, size_t ws_bytes, void *stream, qw_info *info)
+{
+    const double c = alpha * 0.5 * (emax + emin);
+    const double r = std::fabs(alpha) * 0.5 * (emax - emin) + n * std::fabs(beta);
+    const Prepared prep{T, alpha};
+    if (!(r > 0.0)) {
+        // H' = c I (here c = 0 as well): the identity
+        if (psi_out == psi_in) return QW_OK;
+        QW_HIP(hipMemcpyAsync(psi_out, psi_in, (size_t(1) << n) * 2 * sizeof(R), hipMemcpyDeviceToDevice,
+                              reinterpret_cast<hipStream_t>(stream)));
+        return QW_OK;
+    }
+    const double cr[2] = {c, r};
+    return action_impl<R>(n, nullptr, h, J, beta, t, psi_in, psi_out, tol, QW_CHEB, workspace, ws_bytes, stream, info,
+                          cr, nullptr, &prep);
+}
+
+template qw_status prepare_energy<float>(int, const double *, const double *, void *, size_t, void *, EnergyTables *,
+                                         double *, double *);
+template qw_status prepare_energy<double>(int, const double *, const double *, void *, size_t, void *, EnergyTables *,
+                                          double *, double *);
+template qw_status scaled_action<float>(int, const double *, const double *, const EnergyTables &, double, double,
+                                        double, double, double, const void *, void *, double, void *, size_t, void *,
+                                        qw_info *);
+template qw_status scaled_action<double>(int, const double *, const double *, const EnergyTables &, double, double,
+                                         double, double, double, const void *, void *, double, void *, size_t, void *,
+                                         qw_info *);
 
 }  // namespace qw
 
