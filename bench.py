@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-config2", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-poly", action="store_true")
+    ap.add_argument("--no-anneal", action="store_true")
     ap.add_argument("--n32", action="store_true", help="also time the 32-qubit on-the-fly workload (~1 min)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM counters)")
@@ -174,6 +175,62 @@ def poly_leg(torch, qw, synth, np):
             et.append(np.linalg.norm(yt.cpu().numpy() - ex) / nrm)
         out["sincos_n5"][f"s={s:g}"] = {"K_cheb": Kc, "K_taylor": Kt, "median_err_clenshaw_c64": float(np.median(ec)),
                                         "median_err_horner_taylor_c64": float(np.median(et))}
+    return out
+
+
+def anneal_leg(torch, qw, synth, np):
+    """Time-dependent anneal H(t) = s H_P + (1 - s) sum_j X_j, s = t / T, by the
+    fourth-order commutator-free Magnus steps with step sizes from the local
+    error bound.  (1) 8-qubit SK over T = 3 (the setting of Fig. 6): for a sweep
+    of tolerances, the steps, the Chebyshev terms (matrix-vector products) and
+    the error against a reference run of the same integrator at 1e-12 in
+    complex128; beside it the right-hand-side evaluations scipy's DOP853 needs
+    for comparable errors.  (2) 24-qubit SK over T = 2, complex64, tol 1e-4:
+    time and amplitude-terms per second."""
+    import scipy.integrate
+    out = {"n8_fig6": {"cfet": [], "dop853": []}}
+    n, T = 8, 3.0
+    lin = ([0.0, 1.0], [1.0, -1.0])
+    h, J = synth.sk_instance(n, 0)
+    psi = synth.plus_state_torch(n, "cuda", torch.complex128)
+    ref, _, _ = qw.anneal_cfet4(psi, h, J, lin[0], lin[1], T, tol=1e-12)
+    ref = ref.cpu().numpy()
+    for tol in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8):
+        y, info, _ = qw.anneal_cfet4(psi, h, J, lin[0], lin[1], T, tol=tol)
+        err = float(np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref))
+        out["n8_fig6"]["cfet"].append({"tol": tol, "steps": info["steps"], "matvecs": info["terms"],
+                                       "error": err, "err_bound": info["err_bound"]})
+    N = 1 << n
+    idx = np.arange(N)
+    spins = 1 - 2 * ((idx[:, None] >> np.arange(n)) & 1)
+    iu = np.triu_indices(n, 1)
+    E = spins @ h + (spins[:, iu[0]] * spins[:, iu[1]]) @ J
+    flips = [idx ^ (1 << j) for j in range(n)]
+
+    def rhs(t, y):
+        s_ = t / T
+        return -1j * (s_ * E * y + (1 - s_) * sum(y[f] for f in flips))
+
+    y0 = np.full(N, 1 / np.sqrt(N), dtype=np.complex128)
+    for rtol in (1e-4, 1e-6, 1e-8, 1e-10):
+        sol = scipy.integrate.solve_ivp(rhs, (0.0, T), y0, method="DOP853", rtol=rtol, atol=rtol * 1e-2)
+        err = float(np.linalg.norm(sol.y[:, -1] - ref) / np.linalg.norm(ref))
+        out["n8_fig6"]["dop853"].append({"rtol": rtol, "matvecs": int(sol.nfev), "error": err})
+    del psi
+    # (2) throughput at 24 qubits
+    n, T = 24, 2.0
+    h, J = synth.sk_instance(n, 0)
+    psi = synth.plus_state_torch(n, "cuda", torch.complex64)
+    o = torch.empty_like(psi)
+    ws = qw.Workspace.for_problem(n, 64)
+    qw.anneal_cfet4(psi, h, J, lin[0], lin[1], T, tol=1e-4, out=o, workspace=ws)
+    torch.cuda.synchronize()
+    _, info, steps = qw.anneal_cfet4(psi, h, J, lin[0], lin[1], T, tol=1e-4, out=o, workspace=ws, timing=1)
+    out["n24_c64"] = {"T": T, "tol": 1e-4, "steps": info["steps"], "exponentials": info["exponentials"],
+                      "terms": info["terms"], "ms": info["total_ms"], "h_min": info["h_min"], "h_max": info["h_max"],
+                      "amp_terms_per_s": (1 << n) * info["terms"] / (info["total_ms"] * 1e-3)}
+    del psi, o, ws
+    torch.cuda.empty_cache()
     return out
 
 
@@ -385,6 +442,9 @@ def main():
     if not args.no_poly:
         log("[bench] caller polynomials: degree 50 Horner vs Clenshaw; sin+cos error vs radius")
         result["poly"] = poly_leg(torch, qw, synth, np)
+    if not args.no_anneal:
+        log("[bench] anneal: commutator-free Magnus steps (n=8 error sweep, n=24 throughput)")
+        result["anneal"] = anneal_leg(torch, qw, synth, np)
     if args.n32:
         log("[bench] n=32 on-the-fly diagonal")
         result["n32"] = n32_leg(torch, qw, synth)
