@@ -84,7 +84,7 @@ static WsLayout ws_layout(int n, int prec, bool otf)
     L.red = take(2 * sizeof(double));
     L.hj = take((32 + 32 * 31 / 2) * sizeof(double));
     L.q = take((size_t(1) << LB_TAB) * sizeof(double));
-    L.qt = take(4 * (size_t(1) << LB_TAB) * sizeof(float));   // one pair table per orientation
+    L.qt = take(4 * (size_t(1) << TB_WIDE) * sizeof(float));   // one pair table per orientation
     L.coef = (n <= Cfg<float>::TB) ? take((size_t)(KMAX_ONCHIP + 1) * cs) : size_t(-1);
     L.items = take(256);
     L.norms = take(KMAX_MON * sizeof(double));
@@ -189,11 +189,21 @@ static qw_status bound_impl(int n, const R *diag, const double *h, const double 
 }
 
 template <typename R>
-static void launch_pass(const PassArgs<R> &a, int mode, bool otf, uint64_t ntiles, hipStream_t s)
+static void launch_pass(const PassArgs<R> &a, int mode, bool otf, uint64_t ntiles, hipStream_t s, int tb)
 {
     constexpr int TB = Cfg<R>::TB, NT = Cfg<R>::NT;
     const dim3 grid((unsigned)ntiles), block(NT);
     if constexpr (sizeof(R) == 4) {
+        if (tb == TB_WIDE) {
+            constexpr int W = TB_WIDE, WN = NT_WIDE;
+            const dim3 wb(WN);
+            if (otf && mode == PM_START) hipLaunchKernelGGL((k_pass<R, W, WN, PM_START, true>), grid, wb, 0, s, a);
+            else if (otf && mode == PM_FUSED) hipLaunchKernelGGL((k_pass<R, W, WN, PM_FUSED, true>), grid, wb, 0, s, a);
+            else if (mode == PM_START) hipLaunchKernelGGL((k_pass<R, W, WN, PM_START, false>), grid, wb, 0, s, a);
+            else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass<R, W, WN, PM_FUSED, false>), grid, wb, 0, s, a);
+            else hipLaunchKernelGGL((k_pass<R, W, WN, PM_ADD, false>), grid, wb, 0, s, a);
+            return;
+        }
         if (otf && mode == PM_START) { hipLaunchKernelGGL((k_pass<R, TB, NT, PM_START, true>), grid, block, 0, s, a); return; }
         if (otf && mode == PM_FUSED) { hipLaunchKernelGGL((k_pass<R, TB, NT, PM_FUSED, true>), grid, block, 0, s, a); return; }
     }
@@ -458,7 +468,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         }
     }
     const bool horner = poly && poly->horner;
-    const std::vector<PassPlan> plan = plan_passes<R>(n);
+    const int tb = tile_bits_for<R>(n);
+    const std::vector<PassPlan> plan = plan_passes(n, tb, Cfg<R>::LMIN);
     if (info) {
         info->K = K;
         info->a = a;
@@ -513,8 +524,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     const int P = (int)plan.size();
     if (otf) {
         for (int o = 0; o < P; ++o)
-            hipLaunchKernelGGL(k_qtable_orient<0>, dim3((1 << LB_TAB) / 256), dim3(256), 0, s, T.h, n, plan[o].L,
-                               plan[o].g0, plan[o].h, norm_inv_r, qt + (size_t)o * (1 << LB_TAB));
+            hipLaunchKernelGGL(k_qtable_orient<0>, dim3((1 << tb) / 256), dim3(256), 0, s, T.h, n, plan[o].L,
+                               plan[o].g0, plan[o].h, norm_inv_r, qt + (size_t)o * (1 << TB_WIDE));
     }
     timer.mark(1);
     {
@@ -544,7 +555,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         pa.L = pl.L;
         pa.g0 = pl.g0;
         pa.h = pl.h;
-        pa.Qt = qt + (size_t)sp.orient * (1 << LB_TAB);
+        pa.Qt = qt + (size_t)sp.orient * (1 << TB_WIDE);
         pa.pr = R(1);
         pa.pi = R(0);
         pa.dst2 = nullptr;
@@ -579,7 +590,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         pa.cr = (R)cr;
         pa.ci = (R)ci;
         const uint64_t ntiles = N >> (pl.L + pl.h);
-        launch_pass<R>(pa, sp.mode, otf, ntiles, s);
+        launch_pass<R>(pa, sp.mode, otf, ntiles, s, tb);
         ptimer.mark(sp.orient);
         if (sp.mode == PM_FUSED || (sp.mode == PM_START && P == 1)) std::swap(X, Y);
     }
@@ -610,9 +621,9 @@ static qw_status bound_entry(int n, const R *diag, const double *h, const double
 // flipped partner must stay inside the tile.
 int check_plan(int n, int prec)
 {
-    std::vector<PassPlan> plan = (prec == 64) ? plan_passes<float>(n) : plan_passes<double>(n);
+    const int TB = (prec == 64) ? tile_bits_for<float>(n) : tile_bits_for<double>(n);
+    std::vector<PassPlan> plan = plan_passes(n, TB, (prec == 64) ? Cfg<float>::LMIN : Cfg<double>::LMIN);
     const uint64_t N = uint64_t(1) << n;
-    const int TB = (prec == 64) ? Cfg<float>::TB : Cfg<double>::TB;
     int covered_bits = 0;
     for (const PassPlan &p : plan) {
         if (p.L + p.h > TB || p.L + p.h > n) return -1;

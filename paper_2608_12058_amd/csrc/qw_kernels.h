@@ -337,7 +337,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     constexpr int PER = (1 << TB) / (NT * VE);
     constexpr bool DIAG = (MODE != PM_ADD);
     static_assert(PER >= 1, "tile smaller than one vector per thread");
-    __shared__ float fld[OTF ? LB_TAB : 1];
+    __shared__ float fld[OTF ? TB : 1];
     __shared__ float fbase;
 
     const int nv = a.L + a.h;
@@ -345,7 +345,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     const uint64_t base = tile_base(tile, a.L, a.g0, a.h);
 
     if constexpr (OTF) {
-        __shared__ double f64[LB_TAB];
+        __shared__ double f64[TB];
         __shared__ double c64;
         tile_fields_orient(a.hJ, a.n, a.L, a.g0, a.h, base, f64, &c64);
         __syncthreads();
@@ -628,10 +628,12 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct PassPlan { int L, g0, h; };
 
-template <typename R>
-inline std::vector<PassPlan> plan_passes(int n)
+// Orientations of one Clenshaw term for tiles of 2^TB amplitudes: the first
+// takes the low min(n, TB) bits contiguously, the rest split the high bits as
+// evenly as possible into groups of at most TB - LMIN bits, each tile keeping
+// L = TB - h passenger bits for contiguous rows.
+inline std::vector<PassPlan> plan_passes(int n, int TB, int LMIN)
 {
-    constexpr int TB = Cfg<R>::TB, LMIN = Cfg<R>::LMIN;
     std::vector<PassPlan> P;
     const int h0 = std::min(n, TB);
     P.push_back({0, 0, h0});
@@ -647,6 +649,26 @@ inline std::vector<PassPlan> plan_passes(int n)
         }
     }
     return P;
+}
+
+template <typename R> inline std::vector<PassPlan> plan_passes(int n)
+{
+    return plan_passes(n, Cfg<R>::TB, Cfg<R>::LMIN);
+}
+
+// Complex64 can also run 2^14-amplitude tiles (128 KB of LDS, 1024 threads,
+// one workgroup per CU); they are used where they save a global pass per term
+// (n = 23, 24, 32) and the vector still has >= 512 tiles.
+static constexpr int TB_WIDE = 14, NT_WIDE = 1024;
+
+template <typename R> inline int tile_bits_for(int n)
+{
+    if constexpr (sizeof(R) == 4) {
+        if (n >= TB_WIDE + 9 &&
+            plan_passes(n, TB_WIDE, Cfg<R>::LMIN).size() < plan_passes(n, Cfg<R>::TB, Cfg<R>::LMIN).size())
+            return TB_WIDE;
+    }
+    return Cfg<R>::TB;
 }
 
 #define QW_HIP(call)                                                                   \

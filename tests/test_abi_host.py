@@ -95,6 +95,11 @@ def test_pass_counts():
     assert qw.debug_check_plan(13, 64) == 1
     assert qw.debug_check_plan(22, 64) == 2
     assert qw.debug_check_plan(28, 64) == 3
+    # complex64 switches to 2^14-amplitude tiles where that saves a pass
+    assert qw.debug_check_plan(23, 64) == 2
+    assert qw.debug_check_plan(24, 64) == 2
+    assert qw.debug_check_plan(25, 64) == 3
+    assert qw.debug_check_plan(23, 128) == 3
     assert qw.debug_check_plan(12, 128) == 1
     assert qw.debug_check_plan(21, 128) == 2
 

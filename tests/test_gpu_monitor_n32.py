@@ -81,7 +81,7 @@ def test_n32_gamma0_on_the_fly_diagonal(env, oracle_mod):
     h, J = synth.sk_instance(N32, 0)
     psi = synth.plus_state_torch(N32, "cuda", torch.complex64)
     y, info = qw.expm_action(psi, 0.0, 1.0, h=h, J=J, out=psi)
-    assert info["passes"] == 4
+    assert info["passes"] == 3   # 2^14-amplitude tiles: 14 + 9 + 9 bits
     rng = np.random.default_rng(32)
     idx = np.concatenate([[0, (1 << N32) - 1], rng.integers(0, 1 << N32, 510)])
     got = y[torch.as_tensor(idx, device="cuda")].cpu().numpy().astype(np.complex128)
