@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(256) k_normalize_diag(const R *E, uint64_t N, 
 
 
 struct WsLayout {
-    size_t b1, b2, d, part, red, hj, q, qt, coef, items, norms, total;
+    size_t b1, b2, d, part, red, hj, q, qt, ft, coef, items, norms, total;
 };
 
 static WsLayout ws_layout(int n, int prec, bool otf)
@@ -85,6 +85,8 @@ static WsLayout ws_layout(int n, int prec, bool otf)
     L.hj = take((32 + 32 * 31 / 2) * sizeof(double));
     L.q = take((size_t(1) << LB_TAB) * sizeof(double));
     L.qt = take(4 * (size_t(1) << TB_WIDE) * sizeof(float));   // one pair table per orientation
+    // on the fly: per-tile fields of every orientation (tiles of >= 2^13 amplitudes)
+    L.ft = otf ? take(4 * (N >> Cfg<float>::TB) * TILE_FIELDS * sizeof(float)) : size_t(-1);
     L.coef = (n <= Cfg<float>::TB) ? take((size_t)(KMAX_ONCHIP + 1) * cs) : size_t(-1);
     L.items = take(256);
     L.norms = take(KMAX_MON * sizeof(double));
@@ -436,6 +438,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     const double norm_c = (es != 0.0) ? c / es : 0.0, norm_inv_r = es * inv_r;
     R *dn = otf ? nullptr : reinterpret_cast<R *>(ws + L.d);
     float *qt = reinterpret_cast<float *>(ws + L.qt);
+    float *ft = otf ? reinterpret_cast<float *>(ws + L.ft) : nullptr;
+    const uint64_t ft_stride = (N >> Cfg<float>::TB) * TILE_FIELDS;   // floats per orientation
     if (!otf) {
         if (diag) {
             hipLaunchKernelGGL(k_normalize_diag<R>, dim3(grid_for(N, 256 * 8, 1 << 16)), dim3(256), 0, s,
@@ -523,9 +527,14 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     }
     const int P = (int)plan.size();
     if (otf) {
-        for (int o = 0; o < P; ++o)
+        for (int o = 0; o < P; ++o) {
             hipLaunchKernelGGL(k_qtable_orient<0>, dim3((1 << tb) / 256), dim3(256), 0, s, T.h, n, plan[o].L,
                                plan[o].g0, plan[o].h, norm_inv_r, qt + (size_t)o * (1 << TB_WIDE));
+            const uint64_t nt = N >> (plan[o].L + plan[o].h);
+            hipLaunchKernelGGL(k_tile_fields<0>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, T.h, n,
+                               plan[o].L, plan[o].g0, plan[o].h, nt, norm_c, norm_inv_r,
+                               ft + (size_t)o * ft_stride);
+        }
     }
     timer.mark(1);
     {
@@ -538,9 +547,6 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     PassArgs<R> pa{};
     pa.psi = psi;
     pa.d = dn;
-    pa.hJ = T.h;
-    pa.otf_c = norm_c;
-    pa.otf_inv_r = norm_inv_r;
     pa.g = (R)g;
     pa.n = n;
     const std::vector<SchedPass> sched = fused_schedule(K, P);
@@ -556,6 +562,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         pa.g0 = pl.g0;
         pa.h = pl.h;
         pa.Qt = qt + (size_t)sp.orient * (1 << TB_WIDE);
+        pa.Ft = otf ? ft + (size_t)sp.orient * ft_stride : nullptr;
         pa.pr = R(1);
         pa.pi = R(0);
         pa.dst2 = nullptr;
@@ -720,7 +727,7 @@ using namespace qw;
 extern "C" {
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.3 (gfx950, fused passes, Horner)"; }
+const char *qw_version(void) { return "qwexp 0.4 (gfx950, fused passes, wide tiles)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {

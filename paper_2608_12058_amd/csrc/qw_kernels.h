@@ -246,8 +246,7 @@ template <typename R> struct PassArgs {
     const C *psi;  // START, FUSED: v
     const R *d;    // START, FUSED: normalised diagonal (unless on the fly)
     const float *Qt;   // on the fly: Q / r table of this orientation (2^(L+h) entries)
-    const double *hJ;  // on the fly: h then J (device)
-    double otf_c, otf_inv_r;
+    const float *Ft;   // on the fly: per tile, f_i / r (i < L + h) and (C - c) / r at TILE_FIELDS - 1
     R dscale = R(1);   // the diagonal used is d * dscale
     R g;           // gamma / r
     R scale;       // START, ADD: 2 inside the recurrence, 1 for the final step; FUSED: for b_k
@@ -259,42 +258,48 @@ template <typename R> struct PassArgs {
     double *norm_acc = nullptr;   // if set: += sum |b|^2 of the completed vector (atomic, one per block)
 };
 
-// Fields of the on-the-fly diagonal for a tile of any orientation: tile
+// Fields of the on-the-fly diagonal for every tile of one orientation: tile
 // element bit i stands for index bit vb(i) (i < L: bit i; else g0 + i - L);
-// the other index bits are fixed by `base`.  Threads 0..L+h-1 compute
+// the other index bits are fixed by the tile's base.  With
 //   f_i = h_vb(i) + sum_{u fixed} J_{vb(i) u} s_u,
-// thread L+h the constant C = sum_{u fixed} h_u s_u + sum_{u<w fixed} J_uw s_u s_w.
-// With the orientation's pair table Q[e] = sum_{i<j} J_{vb(i) vb(j)} s_i(e) s_j(e),
-// E = C + Q[e] + sum_i f_i s_i(e).
-__device__ inline void tile_fields_orient(const double *hJ, int n, int L, int g0, int h, uint64_t base,
-                                          double *f, double *Cc)
+//   C   = sum_{u fixed} h_u s_u + sum_{u<w fixed} J_uw s_u s_w
+// and the orientation's pair table Q[e] = sum_{i<j} J_{vb(i) vb(j)} s_i(e) s_j(e),
+// E = C + Q[e] + sum_i f_i s_i(e).  One thread per tile writes f_i / r and
+// (C - c) / r in float (sums in double) to Ft[tile * TILE_FIELDS ...].
+static constexpr int TILE_FIELDS = 16;
+
+template <int D = 0>
+__global__ void __launch_bounds__(256) k_tile_fields(const double *hJ, int n, int L, int g0, int h, uint64_t ntiles,
+                                                     double c, double inv_r, float *Ft)
 {
+    const uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= ntiles) return;
     const double *hh = hJ, *J = hJ + n;
-    const int nv = L + h, t = threadIdx.x;
+    const int nv = L + h;
+    const uint64_t base = tile_base(tile, L, g0, h);
     auto isvar = [&](int u) { return u < L || (u >= g0 && u < g0 + h); };
-    if (t < nv) {
-        const int j = (t < L) ? t : g0 + (t - L);
+    auto spin = [&](int u) { return ((base >> u) & 1) ? -1.0 : 1.0; };
+    float *out = Ft + tile * TILE_FIELDS;
+    for (int i = 0; i < nv; ++i) {
+        const int j = (i < L) ? i : g0 + (i - L);
         double acc = hh[j];
         for (int u = 0; u < n; ++u) {
             if (isvar(u)) continue;
-            const double Jju = J[pair_off(n, j < u ? j : u, j < u ? u : j)];
-            acc += ((base >> u) & 1) ? -Jju : Jju;
+            acc += spin(u) * J[pair_off(n, j < u ? j : u, j < u ? u : j)];
         }
-        f[t] = acc;
-    } else if (t == nv) {
-        double acc = 0.0;
-        for (int u = 0; u < n; ++u) {
-            if (isvar(u)) continue;
-            double fu = hh[u];
-            for (int w = u + 1; w < n; ++w) {
-                if (isvar(w)) continue;
-                const double Jw = J[pair_off(n, u, w)];
-                fu += ((base >> w) & 1) ? -Jw : Jw;
-            }
-            acc += ((base >> u) & 1) ? -fu : fu;
-        }
-        *Cc = acc;
+        out[i] = (float)(acc * inv_r);
     }
+    double C = 0.0;
+    for (int u = 0; u < n; ++u) {
+        if (isvar(u)) continue;
+        double fu = hh[u];
+        for (int w = u + 1; w < n; ++w) {
+            if (isvar(w)) continue;
+            fu += spin(w) * J[pair_off(n, u, w)];
+        }
+        C += spin(u) * fu;
+    }
+    out[TILE_FIELDS - 1] = (float)((C - c) * inv_r);
 }
 
 // Pair table of one orientation, scaled: Qt[e] = Q[e] / r in float.
@@ -345,12 +350,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     const uint64_t base = tile_base(tile, a.L, a.g0, a.h);
 
     if constexpr (OTF) {
-        __shared__ double f64[TB];
-        __shared__ double c64;
-        tile_fields_orient(a.hJ, a.n, a.L, a.g0, a.h, base, f64, &c64);
-        __syncthreads();
-        if ((int)threadIdx.x < nv) fld[threadIdx.x] = (float)(f64[threadIdx.x] * a.otf_inv_r);
-        if (threadIdx.x == 0) fbase = (float)((c64 - a.otf_c) * a.otf_inv_r);
+        static_assert(TB < TILE_FIELDS, "tile fields and the constant fit one record");
+        const float *ft = a.Ft + tile * TILE_FIELDS;
+        if ((int)threadIdx.x < nv) fld[threadIdx.x] = ft[threadIdx.x];
+        if (threadIdx.x == 0) fbase = ft[TILE_FIELDS - 1];
     }
 
     V own[PER], accv[PER];
@@ -411,11 +414,22 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     };
     // Diagonal of element ee (global index idx): loaded from d (after the
     // barrier, to keep it out of the registers held across it) or rebuilt from
-    // the tile fields.
+    // the tile fields.  Rebuilt, the linear part sum_j s_j f_j splits by the
+    // bits of ee = (q NT + thread) VE + v: the thread's bits give one partial
+    // sum per thread (tpart), so each element adds only its q bits and bit 0.
+    constexpr int LOG_NT = (NT >= 1024) ? 10 : (NT >= 512) ? 9 : (NT >= 256) ? 8 : 7;
+    static_assert((1 << LOG_NT) == NT, "power-of-two block");
+    float tpart = 0.f;
+    if constexpr (OTF) {
+        static_assert(VE == 2, "the on-the-fly diagonal is complex64 only");
+        for (int j = 0; j < LOG_NT; ++j)
+            if (1 + j < nv) tpart += ((threadIdx.x >> j) & 1) ? -fld[1 + j] : fld[1 + j];
+    }
     auto diag_of = [&](uint64_t idx, uint32_t ee) -> R {
         if constexpr (OTF) {
-            float s = fbase + a.Qt[ee];
-            for (int j = 0; j < nv; ++j) s += ((ee >> j) & 1) ? -fld[j] : fld[j];
+            float s = fbase + a.Qt[ee] + tpart;
+            for (int j = 1 + LOG_NT; j < nv; ++j) s += ((ee >> j) & 1) ? -fld[j] : fld[j];
+            s += (ee & 1) ? -fld[0] : fld[0];
             return (R)s;
         } else {
             return a.d[idx] * a.dscale;
