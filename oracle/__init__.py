@@ -23,6 +23,8 @@ quantum annealing":
   O6 ``anneal_cfet4``        fourth-order commutator-free Magnus steps for a
                              time-dependent anneal (sec. III.B), each exponential
                              by O1.
+  O7 ``remez_parity``        best approximation by the Remez exchange, the
+                             independent check of the CF coefficients (sec. II.C).
   O5 ``horner``              Horner's rule for a polynomial in the monomial basis
                              (Alg. 1), with ``clenshaw`` the evaluation of a
                              caller's Chebyshev series; ``sincos_*_coeffs`` give
@@ -502,6 +504,68 @@ def _cf_parts(a: float, K: int, tail_cut: float = 1e-17):
     coef += pc[:K + 1] if len(pc) >= K + 1 else np.pad(pc, (0, K + 1 - len(pc)))
     coef -= 1j * (ps[:K + 1] if len(ps) >= K + 1 else np.pad(ps, (0, K + 1 - len(ps))))
     return coef, abs(lc) + abs(ls)
+
+
+def remez_parity(f, parity: int, deg: int, grid: int = 40001, iters: int = 60,
+                 rtol: float = 1e-9) -> tuple[np.ndarray, float]:
+    """Best (minimax) approximation on [-1, 1] of an even (parity 0) or odd
+    (parity 1) function f by polynomials of the same parity and degree <= deg,
+    by the Remez exchange (the reference the paper contrasts CF with, sec. II.C).
+
+    By symmetry the problem lives on [0, 1] with the basis T_{2j} (even) or
+    T_{2j+1} (odd), j = 0..m, which is a Haar system there (polynomials in x^2,
+    times x for odd).  Each step solves sum_j c_j phi_j(x_i) + (-1)^i E = f(x_i)
+    on m + 2 reference points, then moves the reference to alternating extrema
+    of the error on a fine grid (multi-point exchange), until the largest error
+    equals |E| to rtol.  Returns (Chebyshev coefficients of T_0..T_deg, |E|)."""
+    m = (deg - parity) // 2
+    if m < 0:
+        raise ValueError("degree below the parity")
+    orders = 2 * np.arange(m + 1) + parity
+
+    def basis(x):
+        return np.cos(np.outer(np.arccos(np.clip(x, -1.0, 1.0)), orders))
+
+    # fine grid on [0, 1], denser near the ends; x = 0 is dropped for odd f
+    xs = np.sort(0.5 * (1.0 - np.cos(np.pi * np.arange(grid) / (grid - 1))))
+    if parity == 1:
+        xs = xs[1:]
+    fx = f(xs)
+    Bx = basis(xs)
+    y = 0.5 * (1.0 + np.cos(np.pi * np.arange(m + 2)[::-1] / (m + 1)))
+    ref = np.sqrt(y)
+    if parity == 1:
+        ref[0] = max(ref[0], xs[0])
+    E = 0.0
+    c = np.zeros(m + 1)
+    for _ in range(iters):
+        A = np.hstack([basis(ref), ((-1.0) ** np.arange(m + 2))[:, None]])
+        sol = np.linalg.solve(A, f(ref))
+        c, E = sol[:-1], sol[-1]
+        err = fx - Bx @ c
+        # local extrema of the error (ends included), then alternating maxima
+        idx = [0] + [i for i in range(1, len(xs) - 1)
+                     if (err[i] - err[i - 1]) * (err[i + 1] - err[i]) <= 0] + [len(xs) - 1]
+        cand = []
+        for i in idx:
+            if cand and np.sign(err[i]) == np.sign(err[cand[-1]]):
+                if abs(err[i]) > abs(err[cand[-1]]):
+                    cand[-1] = i
+            else:
+                cand.append(i)
+        while len(cand) > m + 2:   # drop the smaller end
+            if abs(err[cand[0]]) < abs(err[cand[-1]]):
+                cand.pop(0)
+            else:
+                cand.pop()
+        emax = float(np.max(np.abs(err)))
+        if len(cand) == m + 2:
+            ref = xs[cand]
+        if emax - abs(E) <= rtol * emax:
+            break
+    out = np.zeros(deg + 1)
+    out[orders] = c
+    return out, float(abs(E))
 
 
 def cf_coeffs(a: float, tol: float) -> tuple[np.ndarray, float]:

@@ -161,3 +161,26 @@ def test_coefficient_errors():
         qw.cheb_coeffs(float("nan"), 1e-6)
     with pytest.raises(qw.QwError):
         qw.cheb_coeffs(500.0, 1e-6, kmax=10)
+
+
+@pytest.mark.parametrize("a,tol", [(8.0, 1e-6), (30.0, 2.0 ** -23), (90.0, 1e-10)])
+def test_library_cf_against_remez(oracle_mod, a, tol):
+    """The library's CF coefficients (qw_cheb_coeffs with QW_CF): the cos and
+    sin parts of sum_m (-i)^m alpha_m T_m are within 0.1 % of the minimax error
+    of their degree found by the oracle's Remez exchange, and the reported
+    bound |lambda_c| + |lambda_s| equals the sum of the two minimax errors."""
+    alpha, bound = qw.cheb_coeffs(a, tol, "cf")
+    K = len(alpha) - 1
+    m = np.arange(K + 1)
+    cos_c = np.where(m % 2 == 0, alpha * (-1.0) ** (m // 2), 0.0)
+    sin_c = np.where(m % 2 == 1, alpha * (-1.0) ** ((m - 1) // 2), 0.0)
+    x = np.cos(np.linspace(0, np.pi, 40001))
+    kc = K if K % 2 == 0 else K - 1
+    ks = K if K % 2 == 1 else K - 1
+    _, Ec = oracle_mod.remez_parity(lambda t: np.cos(a * t), 0, kc)
+    _, Es = oracle_mod.remez_parity(lambda t: np.sin(a * t), 1, ks)
+    ec = np.max(np.abs(np.polynomial.chebyshev.chebval(x, cos_c) - np.cos(a * x)))
+    es = np.max(np.abs(np.polynomial.chebyshev.chebval(x, sin_c) - np.sin(a * x)))
+    assert ec <= Ec * 1.001 + 1e-15 and es <= Es * 1.001 + 1e-15
+    assert abs(bound / (Ec + Es) - 1) < 1e-3
+    assert bound <= tol

@@ -532,3 +532,55 @@ def test_pins_catch_a_shifted_horner_coefficient(oracle_mod, monkeypatch):
     H = oracle_mod.hamiltonian_dense(n, d, 0.21)
     ref = sum(a[m] * (np.linalg.matrix_power(H, m) @ v) for m in range(len(a)))
     assert rel(oracle_mod.horner(n, a, d, 0.21, v), ref) > 1e-3
+
+
+# ---------------------------------------------------------------- O7: Remez exchange, minimax check of CF
+
+@pytest.mark.parametrize("m", [1, 3, 6, 10])
+def test_remez_closed_forms(oracle_mod, m):
+    """The best approximation of x^(n) by polynomials of degree n - 2 (same
+    parity) on [-1, 1] has error 2^(1-n) (x^n - T_n / 2^(n-1))."""
+    _, E = oracle_mod.remez_parity(lambda x: x ** (2 * m + 2), 0, 2 * m)
+    assert abs(E / 2.0 ** -(2 * m + 1) - 1) < 1e-6
+    _, E = oracle_mod.remez_parity(lambda x: x ** (2 * m + 3), 1, 2 * m + 1)
+    assert abs(E / 2.0 ** -(2 * m + 2) - 1) < 1e-6
+
+
+@pytest.mark.parametrize("parity,deg,a", [(0, 12, 9.0), (1, 15, 13.0)])
+def test_remez_equioscillates(oracle_mod, parity, deg, a):
+    """The error of the Remez result takes +-E alternately at m + 2 points of
+    [0, 1] (the alternation theorem for the parity-restricted system)."""
+    f = (lambda x: np.cos(a * x)) if parity == 0 else (lambda x: np.sin(a * x))
+    c, E = oracle_mod.remez_parity(f, parity, deg)
+    x = 0.5 * (1 - np.cos(np.pi * np.arange(200001) / 200000))
+    e = f(x) - np.polynomial.chebyshev.chebval(x, c)
+    assert np.max(np.abs(e)) <= E * (1 + 1e-6)
+    m = (deg - parity) // 2
+    assert _alternations(e, E * (1 - 1e-5)) >= m + 2
+
+
+CF_CASES = [(5.0, 4), (5.0, 10), (20.0, 20), (20.0, 26), (60.0, 60), (60.0, 66)]
+
+
+def _parts(oracle_mod, a):
+    Jm = oracle_mod._bessel_table(a)
+    mm = np.arange(len(Jm))
+    ac = np.where(mm % 2 == 0, 2.0 * (-1.0) ** (mm // 2) * Jm, 0.0)
+    ac[0] = Jm[0]
+    as_ = np.where(mm % 2 == 1, 2.0 * (-1.0) ** ((mm - 1) // 2) * Jm, 0.0)
+    return ac, as_
+
+
+@pytest.mark.parametrize("a,deg", CF_CASES)
+def test_cf_is_minimax_by_remez(oracle_mod, a, deg):
+    """The CF estimate |lambda| and the sampled error of the CF polynomial both
+    equal the minimax error found by the Remez exchange (sec. II.C: CF is close
+    to the best approximation at a fraction of the cost)."""
+    ac, as_ = _parts(oracle_mod, a)
+    x = np.cos(np.linspace(0, np.pi, 40001))
+    for parity, coefs, f, d in ((0, ac, np.cos, deg), (1, as_, np.sin, deg + 1)):
+        p, lam = oracle_mod.cf_real(coefs, d + 1)
+        _, Estar = oracle_mod.remez_parity(lambda t: f(a * t), parity, d)
+        err = np.max(np.abs(np.polynomial.chebyshev.chebval(x, p) - f(a * x)))
+        assert abs(abs(lam) / Estar - 1) < 1e-4
+        assert Estar * (1 - 1e-6) <= err <= Estar * (1 + 1e-4)
