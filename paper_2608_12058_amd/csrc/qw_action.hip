@@ -190,28 +190,33 @@ static qw_status bound_impl(int n, const R *diag, const double *h, const double 
     return QW_OK;
 }
 
-template <typename R>
-static void launch_pass(const PassArgs<R> &a, int mode, bool otf, uint64_t ntiles, hipStream_t s, int tb)
+template <typename R, int TB, int NT, bool WITH_OTF>
+static void launch_shape(const PassArgs<R> &a, int mode, bool otf, uint64_t ntiles, hipStream_t s)
 {
-    constexpr int TB = Cfg<R>::TB, NT = Cfg<R>::NT;
     const dim3 grid((unsigned)ntiles), block(NT);
-    if constexpr (sizeof(R) == 4) {
-        if (tb == TB_WIDE) {
-            constexpr int W = TB_WIDE, WN = NT_WIDE;
-            const dim3 wb(WN);
-            if (otf && mode == PM_START) hipLaunchKernelGGL((k_pass<R, W, WN, PM_START, true>), grid, wb, 0, s, a);
-            else if (otf && mode == PM_FUSED) hipLaunchKernelGGL((k_pass<R, W, WN, PM_FUSED, true>), grid, wb, 0, s, a);
-            else if (mode == PM_START) hipLaunchKernelGGL((k_pass<R, W, WN, PM_START, false>), grid, wb, 0, s, a);
-            else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass<R, W, WN, PM_FUSED, false>), grid, wb, 0, s, a);
-            else hipLaunchKernelGGL((k_pass<R, W, WN, PM_ADD, false>), grid, wb, 0, s, a);
-            return;
-        }
+    if constexpr (WITH_OTF) {
         if (otf && mode == PM_START) { hipLaunchKernelGGL((k_pass<R, TB, NT, PM_START, true>), grid, block, 0, s, a); return; }
         if (otf && mode == PM_FUSED) { hipLaunchKernelGGL((k_pass<R, TB, NT, PM_FUSED, true>), grid, block, 0, s, a); return; }
     }
     if (mode == PM_START) hipLaunchKernelGGL((k_pass<R, TB, NT, PM_START, false>), grid, block, 0, s, a);
     else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass<R, TB, NT, PM_FUSED, false>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k_pass<R, TB, NT, PM_ADD, false>), grid, block, 0, s, a);
+}
+
+// Launches one pass in the tile shape chosen for the call (the on-the-fly
+// diagonal exists for the complex64 default and wide shapes, n >= 31).
+template <typename R>
+static void launch_pass(const PassArgs<R> &a, int mode, bool otf, uint64_t ntiles, hipStream_t s, TileCfg cfg)
+{
+    if constexpr (sizeof(R) == 4) {
+        if (cfg.tb == TB_WIDE) return launch_shape<R, TB_WIDE, NT_WIDE, true>(a, mode, otf, ntiles, s);
+        if (cfg.tb == TB_NARROW) return launch_shape<R, TB_NARROW, NT_NARROW, false>(a, mode, otf, ntiles, s);
+        if (cfg.nt == NT_MID) return launch_shape<R, Cfg<R>::TB, NT_MID, false>(a, mode, otf, ntiles, s);
+        return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, true>(a, mode, otf, ntiles, s);
+    } else {
+        if (cfg.nt == NT_NARROW) return launch_shape<R, TB_NARROW, NT_NARROW, false>(a, mode, otf, ntiles, s);
+        return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, false>(a, mode, otf, ntiles, s);
+    }
 }
 
 // Read back ||b_k||^2 (k = 1..K-1), ||y||^2 (slot 0) and ||v||^2 (slot K+1);
@@ -472,7 +477,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         }
     }
     const bool horner = poly && poly->horner;
-    const int tb = tile_bits_for<R>(n);
+    const TileCfg cfg = tile_cfg_for<R>(n);
+    const int tb = cfg.tb;
     const std::vector<PassPlan> plan = plan_passes(n, tb, Cfg<R>::LMIN);
     if (info) {
         info->K = K;
@@ -597,7 +603,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         pa.cr = (R)cr;
         pa.ci = (R)ci;
         const uint64_t ntiles = N >> (pl.L + pl.h);
-        launch_pass<R>(pa, sp.mode, otf, ntiles, s, tb);
+        launch_pass<R>(pa, sp.mode, otf, ntiles, s, cfg);
         ptimer.mark(sp.orient);
         if (sp.mode == PM_FUSED || (sp.mode == PM_START && P == 1)) std::swap(X, Y);
     }
@@ -628,7 +634,7 @@ static qw_status bound_entry(int n, const R *diag, const double *h, const double
 // flipped partner must stay inside the tile.
 int check_plan(int n, int prec)
 {
-    const int TB = (prec == 64) ? tile_bits_for<float>(n) : tile_bits_for<double>(n);
+    const int TB = (prec == 64) ? tile_cfg_for<float>(n).tb : tile_cfg_for<double>(n).tb;
     std::vector<PassPlan> plan = plan_passes(n, TB, (prec == 64) ? Cfg<float>::LMIN : Cfg<double>::LMIN);
     const uint64_t N = uint64_t(1) << n;
     int covered_bits = 0;

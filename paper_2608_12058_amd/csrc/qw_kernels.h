@@ -670,19 +670,38 @@ template <typename R> inline std::vector<PassPlan> plan_passes(int n)
     return plan_passes(n, Cfg<R>::TB, Cfg<R>::LMIN);
 }
 
-// Complex64 can also run 2^14-amplitude tiles (128 KB of LDS, 1024 threads,
-// one workgroup per CU); they are used where they save a global pass per term
-// (n = 23, 24, 32) and the vector still has >= 512 tiles.
+// Tile shapes besides the default one.  Wide: complex64 2^14-amplitude tiles
+// (128 KB of LDS, 1024 threads, one workgroup per CU), used where they save a
+// global pass per term (n = 23, 24, 32) and the vector still has >= 512 tiles.
+// Narrow: 2^12-amplitude tiles with 1024 threads, i.e. 4 (complex64) or 4
+// (complex128) amplitudes per thread instead of 16 / 8, for small vectors
+// (n <= 20 / 21) where one pass would otherwise run too few waves to hide the
+// latency of its load, barrier and store; used only where the pass count stays
+// the same.  Complex64 at n = 21 keeps 2^13 tiles (two orientations) with 1024
+// threads.  Measured per term: n = 21 19.0 us with 1024 threads against 24.7
+// with 512; at n = 22 and n = 28 the 512-thread shape is faster (36.3 against
+// 38.4 us, 3.62 against 3.75 ms).
 static constexpr int TB_WIDE = 14, NT_WIDE = 1024;
+static constexpr int TB_NARROW = 12, NT_NARROW = 1024;
+static constexpr int NT_MID = 1024;   // complex64 2^13 tiles, 8 amplitudes per thread
 
-template <typename R> inline int tile_bits_for(int n)
+struct TileCfg {
+    int tb, nt;
+};
+
+template <typename R> inline TileCfg tile_cfg_for(int n)
 {
+    constexpr int TB = Cfg<R>::TB, LMIN = Cfg<R>::LMIN;
     if constexpr (sizeof(R) == 4) {
-        if (n >= TB_WIDE + 9 &&
-            plan_passes(n, TB_WIDE, Cfg<R>::LMIN).size() < plan_passes(n, Cfg<R>::TB, Cfg<R>::LMIN).size())
-            return TB_WIDE;
+        if (n >= TB_WIDE + 9 && plan_passes(n, TB_WIDE, LMIN).size() < plan_passes(n, TB, LMIN).size())
+            return {TB_WIDE, NT_WIDE};
+        if (n > TB && n <= 20 && plan_passes(n, TB_NARROW, LMIN).size() == plan_passes(n, TB, LMIN).size())
+            return {TB_NARROW, NT_NARROW};
+        if (n == 21) return {TB, NT_MID};
+    } else {
+        if (n > TB && n <= 21) return {TB_NARROW, NT_NARROW};
     }
-    return Cfg<R>::TB;
+    return {TB, Cfg<R>::NT};
 }
 
 #define QW_HIP(call)                                                                   \
