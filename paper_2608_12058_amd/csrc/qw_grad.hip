@@ -64,15 +64,16 @@ __device__ inline void block_add2(double x, double y, double *out)
     }
 }
 
-// One pass of the adjoint step k -> k+1 (see the file comment).
-template <bool START>
-__global__ void __launch_bounds__(GNT) k_adj_pass(AdjArgs a)
+// One pass of the adjoint step k -> k+1 (see the file comment), on tiles of
+// 2^TB amplitudes with NT threads (the shapes of the forward passes).
+template <bool START, int TB, int NT>
+__global__ void __launch_bounds__(NT) k_adj_pass(AdjArgs a)
 {
     using C = float2;
     using V = CVec<float>;
     constexpr int VE = V::N;
-    constexpr int PER = (1 << GTB) / (GNT * VE);
-    __shared__ C lds[1 << GTB];
+    constexpr int PER = (1 << TB) / (NT * VE);
+    __shared__ C lds[1 << TB];
     const uint32_t TE = 1u << (a.L + a.h);
     const uint64_t base = tile_base(blockIdx.x, a.L, a.g0, a.h);
     V own[PER], pv[PER], bn[PER];
@@ -80,7 +81,7 @@ __global__ void __launch_bounds__(GNT) k_adj_pass(AdjArgs a)
     float er[START ? PER : 1][VE], gg[START ? PER : 1][VE];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const uint32_t e = (uint32_t)(q * GNT + threadIdx.x) * VE;
+        const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
         if (e < TE) {
             const uint64_t idx = tile_index(base, e, a.L, a.g0);
             own[q] = *reinterpret_cast<const V *>(a.beta + idx);
@@ -108,7 +109,7 @@ __global__ void __launch_bounds__(GNT) k_adj_pass(AdjArgs a)
     double acc_dt = 0.0, acc_dg = 0.0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const uint32_t e = (uint32_t)(q * GNT + threadIdx.x) * VE;
+        const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
         if (e < TE) {
             const uint64_t idx = tile_index(base, e, a.L, a.g0);
             V out;
@@ -304,10 +305,50 @@ struct GradLayout {
     int nwin, nckpt, ntiles_lo, npar;
 };
 
+// Launch helpers over the tile shapes the forward path chooses (tile_cfg_for).
+template <int TB, int NT>
+static void grad_pass_shape(const PassArgs<float> &pa, int mode, uint64_t ntiles, hipStream_t s)
+{
+    if (mode == PM_START) hipLaunchKernelGGL((k_pass<float, TB, NT, PM_START, false>), dim3((unsigned)ntiles), dim3(NT), 0, s, pa);
+    else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass<float, TB, NT, PM_FUSED, false>), dim3((unsigned)ntiles), dim3(NT), 0, s, pa);
+    else hipLaunchKernelGGL((k_pass<float, TB, NT, PM_ADD, false>), dim3((unsigned)ntiles), dim3(NT), 0, s, pa);
+}
+
+static void launch_grad_pass(const PassArgs<float> &pa, int mode, uint64_t ntiles, TileCfg cfg, hipStream_t s)
+{
+    if (cfg.tb == TB_NARROW) grad_pass_shape<TB_NARROW, NT_NARROW>(pa, mode, ntiles, s);
+    else if (cfg.nt == NT_MID) grad_pass_shape<GTB, NT_MID>(pa, mode, ntiles, s);
+    else grad_pass_shape<GTB, GNT>(pa, mode, ntiles, s);
+}
+
+template <int TB, int NT>
+static void adj_pass_shape(const AdjArgs &aa, bool start, uint64_t ntiles, hipStream_t s)
+{
+    if (start) hipLaunchKernelGGL((k_adj_pass<true, TB, NT>), dim3((unsigned)ntiles), dim3(NT), 0, s, aa);
+    else hipLaunchKernelGGL((k_adj_pass<false, TB, NT>), dim3((unsigned)ntiles), dim3(NT), 0, s, aa);
+}
+
+// The adjoint pass holds five vectors per element (256 VGPRs with 512 threads
+// on 2^13 tiles): it always runs 1024 threads, 4 or 8 amplitudes per thread.
+static void launch_adj_pass(const AdjArgs &aa, bool start, uint64_t ntiles, TileCfg cfg, hipStream_t s)
+{
+    if (cfg.tb == TB_NARROW) adj_pass_shape<TB_NARROW, NT_NARROW>(aa, start, ntiles, s);
+    else adj_pass_shape<GTB, NT_MID>(aa, start, ntiles, s);
+}
+
+// Tile shape of the gradient's passes: the action's choice, without the wide
+// 2^14 tiles (whose adjoint pass would not fit the register file).
+static TileCfg grad_cfg(int n)
+{
+    const TileCfg c = tile_cfg_for<float>(n);
+    return (c.tb == TB_WIDE) ? TileCfg{GTB, GNT} : c;
+}
+
 static int grad_window(int ckpt_every, int K) { return (ckpt_every <= 0 || ckpt_every > K) ? K : ckpt_every; }
 
 static GradLayout grad_layout(int n, int S, const int *Kb, int ckpt_every)
 {
+    const int tb = grad_cfg(n).tb;
     const size_t N = size_t(1) << n;
     GradLayout L{};
     size_t off = 0;
@@ -321,7 +362,7 @@ static GradLayout grad_layout(int n, int S, const int *Kb, int ckpt_every)
         L.nwin = std::max(L.nwin, C);
         L.nckpt += 2 * (W - 1);
     }
-    L.ntiles_lo = (n > GTB) ? (int)(N >> GTB) : 1;
+    L.ntiles_lo = (n > tb) ? (int)(N >> tb) : 1;
     L.npar = n + n * (n - 1) / 2;
     L.states = take(N * 8 * (S + 1));
     L.erel = take(N * 4);
@@ -435,7 +476,8 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
     QW_HIP(hipMemcpyAsync(states, psi0, N * sizeof(C), hipMemcpyDeviceToDevice, s));
 
     // segment plans
-    const std::vector<PassPlan> plan = plan_passes<float>(n);
+    const TileCfg cfg = grad_cfg(n);
+    const std::vector<PassPlan> plan = plan_passes(n, cfg.tb, Cfg<float>::LMIN);
     const int P = (int)plan.size();
     std::vector<SegPlan> seg(S);
     int ck_next = 0;
@@ -496,10 +538,7 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
         pa.h = plan[p].h;
         pa.dscale = (float)sp.inv_r;
         const uint64_t ntiles = N >> (plan[p].L + plan[p].h);
-        if (p == 0)
-            hipLaunchKernelGGL((k_pass<float, GTB, GNT, PM_START, false>), dim3((unsigned)ntiles), dim3(GNT), 0, s, pa);
-        else
-            hipLaunchKernelGGL((k_pass<float, GTB, GNT, PM_ADD, false>), dim3((unsigned)ntiles), dim3(GNT), 0, s, pa);
+        launch_grad_pass(pa, p == 0 ? PM_START : PM_ADD, ntiles, cfg, s);
     };
     const int eg_grid = grid_for(N / 2, 256 * 4, 1 << 16);
     const uint32_t TEw = (uint32_t)std::min<uint64_t>(N, uint64_t(1) << GTB);
@@ -646,8 +685,7 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
                     aa.h = plan[p].h;
                     aa.part = part + (size_t)2 * L.ntiles_lo * p;
                     const uint64_t ntiles = N >> (plan[p].L + plan[p].h);
-                    if (p == 0) hipLaunchKernelGGL(k_adj_pass<true>, dim3((unsigned)ntiles), dim3(GNT), 0, s, aa);
-                    else hipLaunchKernelGGL(k_adj_pass<false>, dim3((unsigned)ntiles), dim3(GNT), 0, s, aa);
+                    launch_adj_pass(aa, p == 0, ntiles, cfg, s);
                 }
                 prevp = Acur;
                 std::swap(Acur, Bnxt);
