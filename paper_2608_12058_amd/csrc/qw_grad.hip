@@ -518,16 +518,21 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
         if (ck_next > std::max(L.nckpt, 1)) { set_error("internal: checkpoint slots exceeded"); return QW_ENOCONV; }
     }
 
-    auto launch_clenshaw_pass = [&](int p, const C *b1, const C *acc, C *dst, double cr, double ci, double scale,
-                                    float pr, float pi, const SegPlan &sp, const C *v) {
+    // One pass of the fused schedule (mode START / ADD / FUSED, see pass_tile):
+    // b1 = b_{k+1}; acc = partial or b_{k+2}; dst (and dst2 for FUSED).
+    auto launch_clenshaw_pass = [&](int mode, int p, const C *b1, const C *acc, C *dst, C *dst2, double cr,
+                                    double ci, double scale, double scale2, float pr, float pi, const SegPlan &sp,
+                                    const C *v) {
         PassArgs<float> pa{};
         pa.b1 = b1;
         pa.acc = acc;
         pa.dst = dst;
+        pa.dst2 = dst2;
         pa.psi = v;
         pa.d = erel;
         pa.g = (float)sp.g;
         pa.scale = (float)scale;
+        pa.scale2 = (float)scale2;
         pa.cr = (float)cr;
         pa.ci = (float)ci;
         pa.pr = pr;
@@ -538,7 +543,7 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
         pa.h = plan[p].h;
         pa.dscale = (float)sp.inv_r;
         const uint64_t ntiles = N >> (plan[p].L + plan[p].h);
-        launch_grad_pass(pa, p == 0 ? PM_START : PM_ADD, ntiles, cfg, s);
+        launch_grad_pass(pa, mode, ntiles, cfg, s);
     };
     const int eg_grid = grid_for(N / 2, 256 * 4, 1 << 16);
     const uint32_t TEw = (uint32_t)std::min<uint64_t>(N, uint64_t(1) << GTB);
@@ -559,24 +564,38 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
                                reinterpret_cast<CVec<float> *>(y), (float)pr, (float)pi, (uint64_t)(N / 2));
             continue;
         }
-        C *X1 = vec(L.A, 0), *X2 = vec(L.B, 0);
+        // fused schedule in two ping-pong buffers; X holds the last completed b_k
+        C *X = vec(L.A, 0), *Y = vec(L.B, 0);
         coef_of(sp.alpha, sp.K, cr, ci);
-        hipLaunchKernelGGL(k_init<float>, dim3(eg_grid), dim3(256), 0, s, reinterpret_cast<const CVec<float> *>(v),
-                           reinterpret_cast<CVec<float> *>(X1), reinterpret_cast<CVec<float> *>(X2), (float)cr,
-                           (float)ci, (uint64_t)(N / 2));
-        if (sp.slot[sp.K] >= 0)
-            QW_HIP(hipMemcpyAsync(vec(L.ckpt, sp.slot[sp.K]), X1, N * sizeof(C), hipMemcpyDeviceToDevice, s));
-        for (int k = sp.K - 1; k >= 0; --k) {
-            coef_of(sp.alpha, k, cr, ci);
-            const bool fin = (k == 0);
-            for (int p = 0; p < P; ++p) {
-                const bool last = (p == P - 1);
-                launch_clenshaw_pass(p, X1, X2, (fin && last) ? y : X2, cr, ci, fin ? 1.0 : 2.0,
-                                     (fin && last) ? sp.ph_r : 1.f, (fin && last) ? sp.ph_i : 0.f, sp, v);
+        hipLaunchKernelGGL(k_scale<float>, dim3(eg_grid), dim3(256), 0, s, reinterpret_cast<const CVec<float> *>(v),
+                           reinterpret_cast<CVec<float> *>(X), (float)cr, (float)ci, (uint64_t)(N / 2));
+        auto save = [&](int k, const C *src) -> qw_status {
+            if (k >= 1 && sp.slot[k] >= 0)
+                QW_HIP(hipMemcpyAsync(vec(L.ckpt, sp.slot[k]), src, N * sizeof(C), hipMemcpyDeviceToDevice, s));
+            return QW_OK;
+        };
+        if ((st = save(sp.K, X)) != QW_OK) return st;
+        auto scale_of = [](int k) { return k == 0 ? 1.0 : 2.0; };
+        for (const SchedPass &ps : fused_schedule(sp.K, P)) {
+            const float pr = ps.fin ? sp.ph_r : 1.f, pi = ps.fin ? sp.ph_i : 0.f;
+            if (ps.mode == PM_START) {
+                coef_of(sp.alpha, ps.k, cr, ci);
+                launch_clenshaw_pass(PM_START, ps.orient, X, (ps.k == sp.K - 1) ? nullptr : Y, ps.fin ? y : Y,
+                                     nullptr, cr, ci, scale_of(ps.k), 0.0, pr, pi, sp, v);
+                if (P == 1 && !ps.fin) {
+                    std::swap(X, Y);
+                    if ((st = save(ps.k, X)) != QW_OK) return st;
+                }
+            } else if (ps.mode == PM_ADD) {
+                launch_clenshaw_pass(PM_ADD, ps.orient, X, Y, ps.fin ? y : Y, nullptr, 0.0, 0.0, scale_of(ps.k), 0.0,
+                                     pr, pi, sp, v);
+            } else {
+                coef_of(sp.alpha, ps.k - 1, cr, ci);
+                launch_clenshaw_pass(PM_FUSED, ps.orient, X, Y, Y, X, cr, ci, scale_of(ps.k), scale_of(ps.k - 1),
+                                     1.f, 0.f, sp, v);
+                std::swap(X, Y);
+                if ((st = save(ps.k, X)) != QW_OK) return st;
             }
-            if (!fin && sp.slot[k] >= 0)
-                QW_HIP(hipMemcpyAsync(vec(L.ckpt, sp.slot[k]), X2, N * sizeof(C), hipMemcpyDeviceToDevice, s));
-            std::swap(X1, X2);
         }
         QW_HIP(hipGetLastError());
     }
@@ -647,13 +666,33 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
                 x2 = (Tw + 2 <= sp.K) ? vec(L.ckpt, sp.slot[Tw + 2]) : nullptr;
                 jstart = Tw;
             }
-            for (int j = jstart; j >= Bw; --j) {
-                coef_of(sp.alpha, j, cr, ci);
-                C *dstj = win + (size_t)(j - Bw) * N;
-                for (int p = 0; p < P; ++p)
-                    launch_clenshaw_pass(p, x1, (p == 0) ? x2 : dstj, dstj, cr, ci, 2.0, 1.f, 0.f, sp, v);
-                x2 = x1;
-                x1 = dstj;
+            // terms j = jstart .. Bw on the fused schedule, b_j kept in win[j - Bw];
+            // every term visits the orientations in the order the forward sweep
+            // used (mirrored when the window starts on the other parity), so the
+            // recomputed b_j equal the forward ones bit for bit
+            {
+                auto Wj = [&](int j) { return win + (size_t)(j - Bw) * N; };
+                auto Bj = [&](int j) -> const C * {
+                    if (j <= jstart) return Wj(j);
+                    return (j == jstart + 1) ? x1 : x2;
+                };
+                const bool mirror = ((sp.K - 1 - jstart) & 1) != 0;
+                for (SchedPass ps : fused_schedule(jstart - Bw + 1, P)) {
+                    if (mirror) ps.orient = P - 1 - ps.orient;
+                    const int j = Bw + ps.k;
+                    if (ps.mode == PM_START) {
+                        coef_of(sp.alpha, j, cr, ci);
+                        launch_clenshaw_pass(PM_START, ps.orient, Bj(j + 1), Bj(j + 2), Wj(j), nullptr, cr, ci, 2.0,
+                                             0.0, 1.f, 0.f, sp, v);
+                    } else if (ps.mode == PM_ADD) {
+                        launch_clenshaw_pass(PM_ADD, ps.orient, Bj(j + 1), Wj(j), Wj(j), nullptr, 0.0, 0.0, 2.0, 0.0,
+                                             1.f, 0.f, sp, v);
+                    } else {
+                        coef_of(sp.alpha, j - 1, cr, ci);
+                        launch_clenshaw_pass(PM_FUSED, ps.orient, Bj(j + 1), Wj(j), Wj(j), Wj(j - 1), cr, ci, 2.0,
+                                             2.0, 1.f, 0.f, sp, v);
+                    }
+                }
             }
             // adjoint steps k = Bw-1 .. Tw-1 with b_{k+1} = win[k + 1 - Bw]
             for (int k = Bw - 1; k <= Tw - 1; ++k) {
