@@ -733,7 +733,7 @@ using namespace qw;
 extern "C" {
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.4 (gfx950, fused passes, wide tiles)"; }
+const char *qw_version(void) { return "qwexp 0.5 (gfx950, fused passes, tile shapes)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {

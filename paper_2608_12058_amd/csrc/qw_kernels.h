@@ -357,7 +357,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     }
 
     V own[PER], accv[PER];
-    V psiv[DIAG ? PER : 1];
+    // psi is prefetched before the barrier, except with the on-the-fly diagonal,
+    // whose extra registers would then spill: there it is read where it is used
+    constexpr bool EARLY_PSI = DIAG && !OTF;
+    V psiv[EARLY_PSI ? PER : 1];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
@@ -370,7 +373,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
 #pragma unroll
                 for (int v = 0; v < VE; ++v) accv[q].v[v] = C{R(0), R(0)};
             }
-            if constexpr (DIAG) psiv[q] = *reinterpret_cast<const V *>(a.psi + idx);
+            if constexpr (EARLY_PSI) psiv[q] = *reinterpret_cast<const V *>(a.psi + idx);
 #pragma unroll
             for (int v = 0; v < VE; ++v) lds[e + v] = own[q].v[v];
         }
@@ -474,7 +477,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
 #pragma unroll
                 for (int v = 0; v < VE; ++v) {
                     const R dd = diag_of(idx + v, e + v);
-                    const C bk = accv[q].v[v], bp = own[q].v[v], ps = psiv[q].v[v];
+                    const C bk = accv[q].v[v], bp = own[q].v[v];
+                    const C ps = EARLY_PSI ? psiv[q].v[v] : a.psi[idx + v];
                     const R hr = dd * bk.x + a.g * sr[v];
                     const R hi = dd * bk.y + a.g * si[v];
                     out.v[v].x = (a.scale2 * hr - a.sub * bp.x) + (a.cr * ps.x - a.ci * ps.y);
@@ -501,7 +505,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                     C o;
                     if constexpr (MODE == PM_START) {
                         const R dd = diag_of(idx + v, ee);
-                        const C b = own[q].v[v], ac = accv[q].v[v], ps = psiv[q].v[v];
+                        const C b = own[q].v[v], ac = accv[q].v[v];
+                        const C ps = EARLY_PSI ? psiv[q].v[v] : a.psi[idx + v];
                         const R hr = dd * b.x + a.g * sr;
                         const R hi = dd * b.y + a.g * si;
                         o.x = (a.scale * hr - a.sub * ac.x) + (a.cr * ps.x - a.ci * ps.y);
