@@ -190,32 +190,38 @@ static qw_status bound_impl(int n, const R *diag, const double *h, const double 
     return QW_OK;
 }
 
-template <typename R, int TB, int NT, bool WITH_OTF>
+template <typename R, int TB, int NT, bool WITH_OTF, bool STREAM>
 static void launch_shape(const PassArgs<R> &a, int mode, bool otf, uint64_t ntiles, hipStream_t s)
 {
     const dim3 grid((unsigned)ntiles), block(NT);
     if constexpr (WITH_OTF) {
-        if (otf && mode == PM_START) { hipLaunchKernelGGL((k_pass<R, TB, NT, PM_START, true>), grid, block, 0, s, a); return; }
-        if (otf && mode == PM_FUSED) { hipLaunchKernelGGL((k_pass<R, TB, NT, PM_FUSED, true>), grid, block, 0, s, a); return; }
+        if (otf && mode == PM_START) { hipLaunchKernelGGL((k_pass<R, TB, NT, PM_START, true, STREAM>), grid, block, 0, s, a); return; }
+        if (otf && mode == PM_FUSED) { hipLaunchKernelGGL((k_pass<R, TB, NT, PM_FUSED, true, STREAM>), grid, block, 0, s, a); return; }
     }
-    if (mode == PM_START) hipLaunchKernelGGL((k_pass<R, TB, NT, PM_START, false>), grid, block, 0, s, a);
-    else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass<R, TB, NT, PM_FUSED, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_pass<R, TB, NT, PM_ADD, false>), grid, block, 0, s, a);
+    if (mode == PM_START) hipLaunchKernelGGL((k_pass<R, TB, NT, PM_START, false, STREAM>), grid, block, 0, s, a);
+    else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass<R, TB, NT, PM_FUSED, false, STREAM>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_pass<R, TB, NT, PM_ADD, false, STREAM>), grid, block, 0, s, a);
 }
 
 // Launches one pass in the tile shape chosen for the call (the on-the-fly
-// diagonal exists for the complex64 default and wide shapes, n >= 31).
+// diagonal exists for the complex64 default and wide shapes, n >= 31; the
+// streaming hint for the shapes used at large n).
 template <typename R>
 static void launch_pass(const PassArgs<R> &a, int mode, bool otf, uint64_t ntiles, hipStream_t s, TileCfg cfg)
 {
     if constexpr (sizeof(R) == 4) {
-        if (cfg.tb == TB_WIDE) return launch_shape<R, TB_WIDE, NT_WIDE, true>(a, mode, otf, ntiles, s);
-        if (cfg.tb == TB_NARROW) return launch_shape<R, TB_NARROW, NT_NARROW, false>(a, mode, otf, ntiles, s);
-        if (cfg.nt == NT_MID) return launch_shape<R, Cfg<R>::TB, NT_MID, false>(a, mode, otf, ntiles, s);
-        return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, true>(a, mode, otf, ntiles, s);
+        if (cfg.tb == TB_WIDE) {
+            if (cfg.stream) return launch_shape<R, TB_WIDE, NT_WIDE, true, true>(a, mode, otf, ntiles, s);
+            return launch_shape<R, TB_WIDE, NT_WIDE, true, false>(a, mode, otf, ntiles, s);
+        }
+        if (cfg.tb == TB_NARROW) return launch_shape<R, TB_NARROW, NT_NARROW, false, false>(a, mode, otf, ntiles, s);
+        if (cfg.nt == NT_MID) return launch_shape<R, Cfg<R>::TB, NT_MID, false, false>(a, mode, otf, ntiles, s);
+        if (cfg.stream) return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, true, true>(a, mode, otf, ntiles, s);
+        return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, true, false>(a, mode, otf, ntiles, s);
     } else {
-        if (cfg.nt == NT_NARROW) return launch_shape<R, TB_NARROW, NT_NARROW, false>(a, mode, otf, ntiles, s);
-        return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, false>(a, mode, otf, ntiles, s);
+        if (cfg.nt == NT_NARROW) return launch_shape<R, TB_NARROW, NT_NARROW, false, false>(a, mode, otf, ntiles, s);
+        if (cfg.stream) return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, false, true>(a, mode, otf, ntiles, s);
+        return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, false, false>(a, mode, otf, ntiles, s);
     }
 }
 

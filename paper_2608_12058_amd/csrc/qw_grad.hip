@@ -66,7 +66,7 @@ __device__ inline void block_add2(double x, double y, double *out)
 
 // One pass of the adjoint step k -> k+1 (see the file comment), on tiles of
 // 2^TB amplitudes with NT threads (the shapes of the forward passes).
-template <bool START, int TB, int NT>
+template <bool START, int TB, int NT, bool STREAM>
 __global__ void __launch_bounds__(NT) k_adj_pass(AdjArgs a)
 {
     using C = float2;
@@ -84,17 +84,17 @@ __global__ void __launch_bounds__(NT) k_adj_pass(AdjArgs a)
         const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
         if (e < TE) {
             const uint64_t idx = tile_index(base, e, a.L, a.g0);
-            own[q] = *reinterpret_cast<const V *>(a.beta + idx);
+            own[q] = ld_v<float, STREAM>(a.beta + idx);
             if (a.prev) {
-                pv[q] = *reinterpret_cast<const V *>(a.prev + idx);
+                pv[q] = ld_v<float, STREAM>(a.prev + idx);
             } else {
 #pragma unroll
                 for (int v = 0; v < VE; ++v) pv[q].v[v] = C{0.f, 0.f};
             }
-            bn[q] = *reinterpret_cast<const V *>(a.bnext + idx);
+            bn[q] = ld_v<float, STREAM>(a.bnext + idx);
             if constexpr (START) {
-                vv[q] = *reinterpret_cast<const V *>(a.v + idx);
-                vb[q] = *reinterpret_cast<const V *>(a.vbar + idx);
+                vv[q] = ld_v<float, STREAM>(a.v + idx);
+                vb[q] = ld_v<float, STREAM>(a.vbar + idx);
 #pragma unroll
                 for (int v = 0; v < VE; ++v) {
                     er[q][v] = a.erel[idx + v];
@@ -142,9 +142,9 @@ __global__ void __launch_bounds__(NT) k_adj_pass(AdjArgs a)
                 }
                 out.v[v] = o;
             }
-            *reinterpret_cast<V *>(a.dst + idx) = out;
+            st_v<float, STREAM>(a.dst + idx, out);
             if constexpr (START) {
-                *reinterpret_cast<V *>(a.vbar + idx) = vb[q];
+                st_v<float, STREAM>(a.vbar + idx, vb[q]);
 #pragma unroll
                 for (int v = 0; v < VE; ++v) a.G[idx + v] = gg[q][v];
             }
@@ -306,34 +306,36 @@ struct GradLayout {
 };
 
 // Launch helpers over the tile shapes the forward path chooses (tile_cfg_for).
-template <int TB, int NT>
+template <int TB, int NT, bool STREAM>
 static void grad_pass_shape(const PassArgs<float> &pa, int mode, uint64_t ntiles, hipStream_t s)
 {
-    if (mode == PM_START) hipLaunchKernelGGL((k_pass<float, TB, NT, PM_START, false>), dim3((unsigned)ntiles), dim3(NT), 0, s, pa);
-    else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass<float, TB, NT, PM_FUSED, false>), dim3((unsigned)ntiles), dim3(NT), 0, s, pa);
-    else hipLaunchKernelGGL((k_pass<float, TB, NT, PM_ADD, false>), dim3((unsigned)ntiles), dim3(NT), 0, s, pa);
+    if (mode == PM_START) hipLaunchKernelGGL((k_pass<float, TB, NT, PM_START, false, STREAM>), dim3((unsigned)ntiles), dim3(NT), 0, s, pa);
+    else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass<float, TB, NT, PM_FUSED, false, STREAM>), dim3((unsigned)ntiles), dim3(NT), 0, s, pa);
+    else hipLaunchKernelGGL((k_pass<float, TB, NT, PM_ADD, false, STREAM>), dim3((unsigned)ntiles), dim3(NT), 0, s, pa);
 }
 
 static void launch_grad_pass(const PassArgs<float> &pa, int mode, uint64_t ntiles, TileCfg cfg, hipStream_t s)
 {
-    if (cfg.tb == TB_NARROW) grad_pass_shape<TB_NARROW, NT_NARROW>(pa, mode, ntiles, s);
-    else if (cfg.nt == NT_MID) grad_pass_shape<GTB, NT_MID>(pa, mode, ntiles, s);
-    else grad_pass_shape<GTB, GNT>(pa, mode, ntiles, s);
+    if (cfg.tb == TB_NARROW) grad_pass_shape<TB_NARROW, NT_NARROW, false>(pa, mode, ntiles, s);
+    else if (cfg.nt == NT_MID) grad_pass_shape<GTB, NT_MID, false>(pa, mode, ntiles, s);
+    else if (cfg.stream) grad_pass_shape<GTB, GNT, true>(pa, mode, ntiles, s);
+    else grad_pass_shape<GTB, GNT, false>(pa, mode, ntiles, s);
 }
 
-template <int TB, int NT>
+template <int TB, int NT, bool STREAM>
 static void adj_pass_shape(const AdjArgs &aa, bool start, uint64_t ntiles, hipStream_t s)
 {
-    if (start) hipLaunchKernelGGL((k_adj_pass<true, TB, NT>), dim3((unsigned)ntiles), dim3(NT), 0, s, aa);
-    else hipLaunchKernelGGL((k_adj_pass<false, TB, NT>), dim3((unsigned)ntiles), dim3(NT), 0, s, aa);
+    if (start) hipLaunchKernelGGL((k_adj_pass<true, TB, NT, STREAM>), dim3((unsigned)ntiles), dim3(NT), 0, s, aa);
+    else hipLaunchKernelGGL((k_adj_pass<false, TB, NT, STREAM>), dim3((unsigned)ntiles), dim3(NT), 0, s, aa);
 }
 
 // The adjoint pass holds five vectors per element (256 VGPRs with 512 threads
 // on 2^13 tiles): it always runs 1024 threads, 4 or 8 amplitudes per thread.
 static void launch_adj_pass(const AdjArgs &aa, bool start, uint64_t ntiles, TileCfg cfg, hipStream_t s)
 {
-    if (cfg.tb == TB_NARROW) adj_pass_shape<TB_NARROW, NT_NARROW>(aa, start, ntiles, s);
-    else adj_pass_shape<GTB, NT_MID>(aa, start, ntiles, s);
+    if (cfg.tb == TB_NARROW) adj_pass_shape<TB_NARROW, NT_NARROW, false>(aa, start, ntiles, s);
+    else if (cfg.stream) adj_pass_shape<GTB, NT_MID, true>(aa, start, ntiles, s);
+    else adj_pass_shape<GTB, NT_MID, false>(aa, start, ntiles, s);
 }
 
 // Tile shape of the gradient's passes: the action's choice, without the wide
@@ -341,7 +343,7 @@ static void launch_adj_pass(const AdjArgs &aa, bool start, uint64_t ntiles, Tile
 static TileCfg grad_cfg(int n)
 {
     const TileCfg c = tile_cfg_for<float>(n);
-    return (c.tb == TB_WIDE) ? TileCfg{GTB, GNT} : c;
+    return (c.tb == TB_WIDE) ? TileCfg{GTB, GNT, c.stream} : c;
 }
 
 static int grad_window(int ckpt_every, int K) { return (ckpt_every <= 0 || ckpt_every > K) ? K : ckpt_every; }

@@ -1,8 +1,11 @@
 """GPU parity of qw_expm_action_{c64,c128} against the CPU oracle.
 
 Element-by-element comparisons (relative L2 over the whole vector) at sizes the
-oracle finishes in seconds, spanning the on-chip path (n <= 13), two passes per
-term (n = 14..22 in complex64) and three (n >= 23); at the full 28-qubit
+oracle finishes in seconds, spanning the on-chip path (n <= 13) and every tile
+shape of the multi-pass path: 2^12-amplitude tiles with 1024 threads (n <= 20 in
+complex64, <= 21 in complex128), 2^13 tiles with 1024 threads (n = 21) and 512
+threads (n = 22, and three orientations from n = 25), 2^14 tiles (n = 23, 24);
+at the full 28-qubit
 workload, properties that hold at any size and closed forms evaluated one
 sampled amplitude at a time.
 
@@ -70,8 +73,10 @@ CASES = [
     (14, 1.2, 0.8, 6),
     (17, 0.8, 1.0, 7),
     (20, 1.0, 0.5, 8),
+    (21, 0.9, 0.5, 11),
     (22, 0.7, 0.4, 9),
     (23, 1.0, 0.3, 10),
+    (24, 0.8, 0.2, 12),
 ]
 
 
