@@ -183,28 +183,6 @@ __device__ inline void block_sum_atomic(double x, double *dst)
     }
 }
 
-// b1 = c_K psi, b2 = 0   (Eq. recursion: b_K = c_K v, b_{K+1} = 0)
-template <typename R>
-__global__ void __launch_bounds__(256) k_init(const CVec<R> *psi, CVec<R> *b1, CVec<R> *b2,
-                                              R cr, R ci, uint64_t nvec)
-{
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nvec;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const CVec<R> p = psi[i];
-        CVec<R> o, z;
-#pragma unroll
-        for (int v = 0; v < CVec<R>::N; ++v) {
-            o.v[v].x = cr * p.v[v].x - ci * p.v[v].y;
-            o.v[v].y = cr * p.v[v].y + ci * p.v[v].x;
-            z.v[v].x = R(0);
-            z.v[v].y = R(0);
-        }
-        b1[i] = o;
-        b2[i] = z;
-    }
-}
-
-// *acc += ||x||^2 (double), grid-stride.
 template <typename R>
 __global__ void __launch_bounds__(256) k_norm2(const CVec<R> *x, uint64_t nvec, double *acc)
 {
