@@ -609,7 +609,11 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         pa.cr = (R)cr;
         pa.ci = (R)ci;
         const uint64_t ntiles = N >> (pl.L + pl.h);
-        launch_pass<R>(pa, sp.mode, otf, ntiles, s, cfg);
+        // the streaming hint pays on the strided passes (rows gathered from
+        // far apart); the contiguous first orientation is faster without it
+        TileCfg pcfg = cfg;
+        pcfg.stream = cfg.stream && pl.L > 0;
+        launch_pass<R>(pa, sp.mode, otf, ntiles, s, pcfg);
         ptimer.mark(sp.orient);
         if (sp.mode == PM_FUSED || (sp.mode == PM_START && P == 1)) std::swap(X, Y);
     }
