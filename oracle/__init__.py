@@ -411,11 +411,10 @@ def closed_form_hp0_product_amps(factors: np.ndarray, gamma: float, t: float,
     return amp
 
 
-def closed_form_gamma0_amps(n: int, h: np.ndarray, J: np.ndarray, t: float,
-                            psi_amps: np.ndarray, idx: np.ndarray) -> np.ndarray:
-    """gamma = 0 at sampled indices: exp(-i t E(z)) psi[z], E(z) summed by its
-    definition for each sampled z (pure Python loops; small sample only)."""
-    out = np.empty(len(idx), dtype=np.complex128)
+def energies_at(n: int, h: np.ndarray, J: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    """E(z) = sum_{j<k} J_jk s_j s_k + sum_j h_j s_j at sampled indices z, summed
+    by the definition (pure Python loops; small samples only)."""
+    out = np.empty(len(idx))
     for q, z in enumerate(np.asarray(idx, dtype=np.int64)):
         z = int(z)
         s = [1.0 - 2.0 * ((z >> j) & 1) for j in range(n)]
@@ -425,8 +424,15 @@ def closed_form_gamma0_amps(n: int, h: np.ndarray, J: np.ndarray, t: float,
             for k in range(j + 1, n):
                 e += J[p] * s[j] * s[k]
                 p += 1
-        out[q] = np.exp(-1j * t * e) * psi_amps[q]
+        out[q] = e
     return out
+
+
+def closed_form_gamma0_amps(n: int, h: np.ndarray, J: np.ndarray, t: float,
+                            psi_amps: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    """gamma = 0 at sampled indices: exp(-i t E(z)) psi[z], E(z) summed by its
+    definition for each sampled z."""
+    return np.exp(-1j * t * energies_at(n, h, J, idx)) * np.asarray(psi_amps)
 
 
 # --------------------------------------------------------------------------

@@ -584,3 +584,10 @@ def test_cf_is_minimax_by_remez(oracle_mod, a, deg):
         err = np.max(np.abs(np.polynomial.chebyshev.chebval(x, p) - f(a * x)))
         assert abs(abs(lam) / Estar - 1) < 1e-4
         assert Estar * (1 - 1e-6) <= err <= Estar * (1 + 1e-4)
+
+
+def test_energies_at_matches_full_vector(oracle_mod):
+    n = 9
+    h, J = synth.sk_instance(n, 31)
+    idx = np.arange(1 << n)
+    assert np.allclose(oracle_mod.energies_at(n, h, J, idx), oracle_mod.energies(n, h, J), rtol=0, atol=1e-12)
