@@ -404,7 +404,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBPS, "traffic": traffic,
                      "kernel": "Clenshaw term (all passes), 36 B/amp algorithmic",
-                     "avg_term_us": term_ms * 1e3},
+                     "avg_term_us": term_ms * 1e3,
+                     # HBM rate of the bytes the counters saw per term (traffic), same term time
+                     "traffic_GBps": (traffic / (term_ms * 1e-3) / 1e9) if traffic else None,
+                     "traffic_frac": (traffic / (term_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS) if traffic else None},
         "loop_ms": loop_ms, "setup_ms": setup_ms,
         "loop_amp_terms_per_s": N * K / (loop_ms * 1e-3),
         "passes": passes,
