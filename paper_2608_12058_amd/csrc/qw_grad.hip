@@ -25,20 +25,61 @@ namespace qw {
 static constexpr int GTB = Cfg<float>::TB;   // tile bits of the element-wise kernels
 static constexpr int GNT = Cfg<float>::NT;
 
+// Coefficients of one adjoint step k (see the file comment).
+struct AdjStep {
+    float scale, ckr, cki, gw;   // scale 2 (1 for k = 0), conj(c_k) applied to beta_k, w_k / r
+    double wk, dcr, dci;         // w_k, r dc_k/da
+};
+
 struct AdjArgs {
     const float2 *beta;    // beta_k: its flips over the tile group are summed
-    const float2 *prev;    // START: beta_{k-1} (NULL for k = 0); ADD: partial beta_{k+1}
-    float2 *dst;           // beta_{k+1} (may alias prev)
+    const float2 *prev;    // START: beta_{k-1} (NULL for k = 0); ADD, FUSED: partial beta_{k+1}
+    float2 *dst;           // beta_{k+1}, partial or complete (may alias prev)
+    float2 *dst2;          // FUSED: partial beta_{k+2} (may alias beta)
     const float2 *bnext;   // b_{k+1}
+    const float2 *bnext2;  // FUSED: b_{k+2}
     const float2 *v;       // segment input
     float2 *vbar;          // accumulates conj(c_k) beta_k
     float *G;              // accumulates w_k/r Re(conj(beta_k) b_{k+1})
     const float *erel;     // E - c
     double *part;          // per block: [0] += Re(dc_k <beta_k, v>), [1] += w_k Re<F beta_k, b_{k+1}>
-    float dscale, g, scale, ckr, cki, gw;
-    double wk, dcr, dci;
+    double *part2;         // FUSED: the same for step k + 1
+    float dscale, g;
+    AdjStep st, st2;       // step k; FUSED: step k + 1
     int L, g0, h;
 };
+
+// One element of the first pass of step k: the start of beta_{k+1} and the
+// accumulations that use beta_k (b = beta_k, p = beta_{k-1}, bx = b_{k+1},
+// x = v, (sr, si) = flips of beta_k over the pass's group).
+__device__ __forceinline__ float2 adj_start_elem(const AdjStep &s, float dscale, float g, float er, float2 b,
+                                                 float2 p, float2 bx, float2 x, float sr, float si, float2 &vb,
+                                                 float &gg, double &dt, double &dg)
+{
+    dg += s.wk * (double)(sr * bx.x + si * bx.y);
+    const float d = er * dscale;
+    float2 o;
+    o.x = s.scale * (d * b.x + g * sr) - p.x;
+    o.y = s.scale * (d * b.y + g * si) - p.y;
+    vb.x += s.ckr * b.x + s.cki * b.y;
+    vb.y += s.ckr * b.y - s.cki * b.x;
+    gg += s.gw * (b.x * bx.x + b.y * bx.y);
+    const double pr = (double)b.x * x.x + (double)b.y * x.y;
+    const double pi = (double)b.x * x.y - (double)b.y * x.x;
+    dt += s.dcr * pr - s.dci * pi;
+    return o;
+}
+
+// One element of a later pass of step k: p = partial beta_{k+1}.
+__device__ __forceinline__ float2 adj_add_elem(const AdjStep &s, float g, float2 p, float2 bx, float sr, float si,
+                                               double &dg)
+{
+    dg += s.wk * (double)(sr * bx.x + si * bx.y);
+    float2 o;
+    o.x = p.x + s.scale * g * sr;
+    o.y = p.y + s.scale * g * si;
+    return o;
+}
 
 __device__ inline void block_add2(double x, double y, double *out)
 {
@@ -65,14 +106,23 @@ __device__ inline void block_add2(double x, double y, double *out)
 }
 
 // One pass of the adjoint step k -> k+1 (see the file comment), on tiles of
-// 2^TB amplitudes with NT threads (the shapes of the forward passes).
-template <bool START, int TB, int NT, bool STREAM>
+// 2^TB amplitudes with NT threads (the shapes of the forward passes):
+//  START: first orientation of step k (diagonal, flips, - beta_{k-1}, accumulations);
+//  ADD:   a later orientation of step k;
+//  FUSED: the last orientation of step k, then in the same orientation the
+//         first of step k + 1 from the completed beta_{k+1} re-staged in LDS.
+// The per-element arithmetic is the same in all three (adj_start_elem /
+// adj_add_elem), so a step gives the same bits fused or not.
+enum AdjMode { AM_START = 0, AM_ADD = 1, AM_FUSED = 2 };
+
+template <int MODE, int TB, int NT, bool STREAM>
 __global__ void __launch_bounds__(NT) k_adj_pass(AdjArgs a)
 {
     using C = float2;
     using V = CVec<float>;
     constexpr int VE = V::N;
     constexpr int PER = (1 << TB) / (NT * VE);
+    constexpr bool START = (MODE == AM_START);
     __shared__ C lds[1 << TB];
     const uint32_t TE = 1u << (a.L + a.h);
     const uint64_t base = tile_base(blockIdx.x, a.L, a.g0, a.h);
@@ -106,6 +156,15 @@ __global__ void __launch_bounds__(NT) k_adj_pass(AdjArgs a)
         }
     }
     __syncthreads();
+    auto flips = [&](uint32_t ee, float &sr, float &si) {
+        sr = 0.f;
+        si = 0.f;
+        for (int j = 0; j < a.h; ++j) {
+            const C nb = lds[ee ^ (1u << (a.L + j))];
+            sr += nb.x;
+            si += nb.y;
+        }
+    };
     double acc_dt = 0.0, acc_dg = 0.0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -115,42 +174,67 @@ __global__ void __launch_bounds__(NT) k_adj_pass(AdjArgs a)
             V out;
 #pragma unroll
             for (int v = 0; v < VE; ++v) {
-                const uint32_t ee = e + v;
-                float sr = 0.f, si = 0.f;
-                for (int j = 0; j < a.h; ++j) {
-                    const C nb = lds[ee ^ (1u << (a.L + j))];
-                    sr += nb.x;
-                    si += nb.y;
-                }
-                const C b = own[q].v[v], p = pv[q].v[v], bx = bn[q].v[v];
-                acc_dg += a.wk * (double)(sr * bx.x + si * bx.y);
-                C o;
-                if constexpr (START) {
-                    const float d = er[q][v] * a.dscale;
-                    o.x = a.scale * (d * b.x + a.g * sr) - p.x;
-                    o.y = a.scale * (d * b.y + a.g * si) - p.y;
-                    vb[q].v[v].x += a.ckr * b.x + a.cki * b.y;
-                    vb[q].v[v].y += a.ckr * b.y - a.cki * b.x;
-                    gg[q][v] += a.gw * (b.x * bx.x + b.y * bx.y);
-                    const C x = vv[q].v[v];
-                    const double pr = (double)b.x * x.x + (double)b.y * x.y;
-                    const double pi = (double)b.x * x.y - (double)b.y * x.x;
-                    acc_dt += a.dcr * pr - a.dci * pi;
-                } else {
-                    o.x = p.x + a.scale * a.g * sr;
-                    o.y = p.y + a.scale * a.g * si;
-                }
-                out.v[v] = o;
+                float sr, si;
+                flips(e + v, sr, si);
+                if constexpr (START)
+                    out.v[v] = adj_start_elem(a.st, a.dscale, a.g, er[q][v], own[q].v[v], pv[q].v[v], bn[q].v[v],
+                                              vv[q].v[v], sr, si, vb[q].v[v], gg[q][v], acc_dt, acc_dg);
+                else
+                    out.v[v] = adj_add_elem(a.st, a.g, pv[q].v[v], bn[q].v[v], sr, si, acc_dg);
             }
-            st_v<float, STREAM>(a.dst + idx, out);
-            if constexpr (START) {
-                st_v<float, STREAM>(a.vbar + idx, vb[q]);
+            if constexpr (MODE == AM_FUSED) {
+                pv[q] = out;   // completed beta_{k+1}, kept for the second half
+            } else {
+                st_v<float, STREAM>(a.dst + idx, out);
+                if constexpr (START) {
+                    st_v<float, STREAM>(a.vbar + idx, vb[q]);
 #pragma unroll
-                for (int v = 0; v < VE; ++v) a.G[idx + v] = gg[q][v];
+                    for (int v = 0; v < VE; ++v) a.G[idx + v] = gg[q][v];
+                }
             }
         }
     }
     block_add2(acc_dt, acc_dg, a.part + 2 * blockIdx.x);
+    if constexpr (MODE == AM_FUSED) {
+        // second half: step k + 1 from the completed beta_{k+1} (pv) with
+        // beta_k (own) as the subtracted vector
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
+            if (e < TE) {
+#pragma unroll
+                for (int v = 0; v < VE; ++v) lds[e + v] = pv[q].v[v];
+            }
+        }
+        __syncthreads();
+        double dt2 = 0.0, dg2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
+            if (e < TE) {
+                const uint64_t idx = tile_index(base, e, a.L, a.g0);
+                const V bx = ld_v<float, STREAM>(a.bnext2 + idx);
+                const V x = ld_v<float, STREAM>(a.v + idx);
+                V vbq = ld_v<float, STREAM>(a.vbar + idx);
+                V out;
+#pragma unroll
+                for (int v = 0; v < VE; ++v) {
+                    float sr, si;
+                    flips(e + v, sr, si);
+                    float gq = a.G[idx + v];
+                    out.v[v] = adj_start_elem(a.st2, a.dscale, a.g, a.erel[idx + v], pv[q].v[v], own[q].v[v],
+                                              bx.v[v], x.v[v], sr, si, vbq.v[v], gq, dt2, dg2);
+                    a.G[idx + v] = gq;
+                }
+                st_v<float, STREAM>(a.dst + idx, pv[q]);
+                st_v<float, STREAM>(a.dst2 + idx, out);
+                st_v<float, STREAM>(a.vbar + idx, vbq);
+            }
+        }
+        __syncthreads();   // block_add2's shared sums are reused
+        block_add2(dt2, dg2, a.part2 + 2 * blockIdx.x);
+    }
 }
 
 // Element-wise kernels over tiles of 2^GTB consecutive amplitudes (TE = min(N, 2^GTB)).
@@ -323,19 +407,21 @@ static void launch_grad_pass(const PassArgs<float> &pa, int mode, uint64_t ntile
 }
 
 template <int TB, int NT, bool STREAM>
-static void adj_pass_shape(const AdjArgs &aa, bool start, uint64_t ntiles, hipStream_t s)
+static void adj_pass_shape(const AdjArgs &aa, int mode, uint64_t ntiles, hipStream_t s)
 {
-    if (start) hipLaunchKernelGGL((k_adj_pass<true, TB, NT, STREAM>), dim3((unsigned)ntiles), dim3(NT), 0, s, aa);
-    else hipLaunchKernelGGL((k_adj_pass<false, TB, NT, STREAM>), dim3((unsigned)ntiles), dim3(NT), 0, s, aa);
+    const dim3 g((unsigned)ntiles), b(NT);
+    if (mode == AM_START) hipLaunchKernelGGL((k_adj_pass<AM_START, TB, NT, STREAM>), g, b, 0, s, aa);
+    else if (mode == AM_FUSED) hipLaunchKernelGGL((k_adj_pass<AM_FUSED, TB, NT, STREAM>), g, b, 0, s, aa);
+    else hipLaunchKernelGGL((k_adj_pass<AM_ADD, TB, NT, STREAM>), g, b, 0, s, aa);
 }
 
 // The adjoint pass holds five vectors per element (256 VGPRs with 512 threads
 // on 2^13 tiles): it always runs 1024 threads, 4 or 8 amplitudes per thread.
-static void launch_adj_pass(const AdjArgs &aa, bool start, uint64_t ntiles, TileCfg cfg, hipStream_t s)
+static void launch_adj_pass(const AdjArgs &aa, int mode, uint64_t ntiles, TileCfg cfg, hipStream_t s)
 {
-    if (cfg.tb == TB_NARROW) adj_pass_shape<TB_NARROW, NT_NARROW, false>(aa, start, ntiles, s);
-    else if (cfg.stream) adj_pass_shape<GTB, NT_MID, true>(aa, start, ntiles, s);
-    else adj_pass_shape<GTB, NT_MID, false>(aa, start, ntiles, s);
+    if (cfg.tb == TB_NARROW) adj_pass_shape<TB_NARROW, NT_NARROW, false>(aa, mode, ntiles, s);
+    else if (cfg.stream) adj_pass_shape<GTB, NT_MID, true>(aa, mode, ntiles, s);
+    else adj_pass_shape<GTB, NT_MID, false>(aa, mode, ntiles, s);
 }
 
 // Tile shape of the gradient's passes: the action's choice, without the wide
@@ -696,40 +782,81 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
                     }
                 }
             }
-            // adjoint steps k = Bw-1 .. Tw-1 with b_{k+1} = win[k + 1 - Bw]
-            for (int k = Bw - 1; k <= Tw - 1; ++k) {
-                double ckr, cki, dcr, dci;
-                coef_of(sp.alpha, k, ckr, cki);
-                coef_of(sp.dalpha, k, dcr, dci);
-                const double wk = (k == 0) ? 1.0 : 2.0;
-                AdjArgs aa{};
-                aa.beta = Acur;
-                aa.bnext = win + (size_t)(k + 1 - Bw) * N;
-                aa.v = v;
-                aa.vbar = vbar;
-                aa.G = G;
-                aa.erel = erel;
-                aa.dscale = (float)sp.inv_r;
-                aa.g = (float)sp.g;
-                aa.scale = (k == 0) ? 1.f : 2.f;
-                aa.ckr = (float)ckr;
-                aa.cki = (float)cki;
-                aa.gw = (float)(wk * sp.inv_r);
-                aa.wk = wk;
-                aa.dcr = dcr * sp.r;
-                aa.dci = dci * sp.r;
-                for (int p = 0; p < P; ++p) {
-                    aa.prev = (p == 0) ? prevp : Bnxt;
-                    aa.dst = Bnxt;
-                    aa.L = plan[p].L;
-                    aa.g0 = plan[p].g0;
-                    aa.h = plan[p].h;
-                    aa.part = part + (size_t)2 * L.ntiles_lo * p;
-                    const uint64_t ntiles = N >> (plan[p].L + plan[p].h);
-                    launch_adj_pass(aa, p == 0, ntiles, cfg, s);
+            // adjoint steps k = Bw-1 .. Tw-1 with b_{k+1} = win[k + 1 - Bw].  Step k
+            // visits the orientations in order 0..P-1 (k even) or reversed (k
+            // odd), so its last orientation is the first of step k + 1 and the
+            // two share one FUSED pass whenever b_{k+2} is in the window.  The
+            // order depends on k alone and a partial sum goes to the slot of the
+            // pass's position in its step, so the result does not depend on the
+            // checkpoint interval.
+            {
+                auto orient = [&](int k, int i) { return (k & 1) ? P - 1 - i : i; };
+                auto step_of = [&](int k) {
+                    double ckr, cki, dcr, dci;
+                    coef_of(sp.alpha, k, ckr, cki);
+                    coef_of(sp.dalpha, k, dcr, dci);
+                    const double wk = (k == 0) ? 1.0 : 2.0;
+                    AdjStep st;
+                    st.scale = (k == 0) ? 1.f : 2.f;
+                    st.ckr = (float)ckr;
+                    st.cki = (float)cki;
+                    st.gw = (float)(wk * sp.inv_r);
+                    st.wk = wk;
+                    st.dcr = dcr * sp.r;
+                    st.dci = dci * sp.r;
+                    return st;
+                };
+                auto bwin = [&](int j) { return win + (size_t)(j - Bw) * N; };
+                auto slot = [&](int i) { return part + (size_t)2 * L.ntiles_lo * i; };
+                bool started = false;   // step k was started by the previous fused pass
+                for (int k = Bw - 1; k <= Tw - 1; ++k) {
+                    AdjArgs aa{};
+                    aa.v = v;
+                    aa.vbar = vbar;
+                    aa.G = G;
+                    aa.erel = erel;
+                    aa.dscale = (float)sp.inv_r;
+                    aa.g = (float)sp.g;
+                    aa.st = step_of(k);
+                    aa.beta = Acur;
+                    aa.bnext = bwin(k + 1);
+                    auto launch = [&](int mode, int o) {
+                        aa.L = plan[o].L;
+                        aa.g0 = plan[o].g0;
+                        aa.h = plan[o].h;
+                        launch_adj_pass(aa, mode, N >> (plan[o].L + plan[o].h), cfg, s);
+                    };
+                    if (!started) {
+                        aa.prev = prevp;
+                        aa.dst = Bnxt;
+                        aa.part = slot(0);
+                        launch(AM_START, orient(k, 0));
+                    }
+                    started = false;
+                    for (int i = 1; i <= P - 2; ++i) {
+                        aa.prev = Bnxt;
+                        aa.dst = Bnxt;
+                        aa.part = slot(i);
+                        launch(AM_ADD, orient(k, i));
+                    }
+                    if (P >= 2) {
+                        aa.prev = Bnxt;
+                        aa.dst = Bnxt;
+                        aa.part = slot(P - 1);
+                        if (k + 1 <= Tw - 1) {
+                            aa.dst2 = Acur;          // beta_{k+2} over beta_k
+                            aa.bnext2 = bwin(k + 2);
+                            aa.part2 = slot(0);
+                            aa.st2 = step_of(k + 1);
+                            launch(AM_FUSED, orient(k, P - 1));
+                            started = true;
+                        } else {
+                            launch(AM_ADD, orient(k, P - 1));
+                        }
+                    }
+                    prevp = Acur;
+                    std::swap(Acur, Bnxt);
                 }
-                prevp = Acur;
-                std::swap(Acur, Bnxt);
             }
             QW_HIP(hipGetLastError());
         }
