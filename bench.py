@@ -36,7 +36,7 @@ BYTES_INIT = {64: 24, 128: 48}             # b_K = c_K psi, b_{K+1} = 0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=28, help="qubits (default: the 28-qubit headline workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -355,10 +355,12 @@ def main():
         step()
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
-    infos = []
+    infos, walls = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        infos.append(step(timing=1))
+        ta = time.perf_counter()
+        infos.append(step(timing=1))   # timing=1 returns after the call's last event
+        walls.append((time.perf_counter() - ta) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
@@ -408,7 +410,7 @@ def main():
                      # HBM rate of the bytes the counters saw per term (traffic), same term time
                      "traffic_GBps": (traffic / (term_ms * 1e-3) / 1e9) if traffic else None,
                      "traffic_frac": (traffic / (term_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS) if traffic else None},
-        "loop_ms": loop_ms, "setup_ms": setup_ms,
+        "loop_ms": loop_ms, "setup_ms": setup_ms, "ms_per_step_median": float(np.median(walls)),
         "loop_amp_terms_per_s": N * K / (loop_ms * 1e-3),
         "passes": passes,
     }
