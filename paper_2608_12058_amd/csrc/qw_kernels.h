@@ -268,7 +268,16 @@ template <typename R> struct PassArgs {
     R sub = R(1);  // START, FUSED: weight of the subtracted b_{k+2} (Clenshaw 1, Horner 0)
     int n, L, g0, h;
     double *norm_acc = nullptr;   // if set: += sum |b|^2 of the completed vector (atomic, one per block)
+    int xcd_order = 0;            // 1: blocks take tiles in XCD-major order (xcd_tile)
 };
+
+// Workgroups of a launch are dealt round-robin to the 8 XCDs (block b on XCD
+// b mod 8).  xcd_tile gives the blocks of each XCD a contiguous range of
+// tiles, so tiles that share DRAM pages (neighbouring rows) run on one XCD.
+__device__ __forceinline__ uint64_t xcd_tile(uint32_t b, uint32_t nb)
+{
+    return (nb % 8 == 0) ? (uint64_t)(b % 8) * (nb / 8) + b / 8 : b;
+}
 
 // Fields of the on-the-fly diagonal for every tile of one orientation: tile
 // element bit i stands for index bit vb(i) (i < L: bit i; else g0 + i - L);
@@ -546,7 +555,8 @@ template <typename R, int TB, int NT, int MODE, bool OTF, bool STREAM = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_pass(PassArgs<R> a)
 {
     __shared__ typename Cplx<R>::T lds[1 << TB];
-    pass_tile<R, TB, NT, MODE, OTF, STREAM>(a, blockIdx.x, lds);
+    const uint64_t tile = a.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    pass_tile<R, TB, NT, MODE, OTF, STREAM>(a, tile, lds);
 }
 
 // Whole recurrence of one small instance (n <= TB) inside one workgroup.
