@@ -751,7 +751,7 @@ using namespace qw;
 extern "C" {
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.5 (gfx950, fused passes, tile shapes)"; }
+const char *qw_version(void) { return "qwexp 0.6 (gfx950, fused passes, tile shapes, XCD order)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {
