@@ -137,7 +137,7 @@ typedef struct {
  *                    sum_j 2(|h_j| + sum_k |J_jk|) on ||[H_P, sum_j X_j]||), so no
  *                    trial steps are run; half of tol goes to the series;
  *   step_sizes     : host, may be NULL; receives the first step_cap step sizes;
- *   workspace      : as qw_workspace_bytes(n, 64 or 128, n >= 31);
+ *   workspace      : as qw_workspace_bytes(n, 64 or 128, n >= 31 in complex64);
  *   psi_out        : may alias psi_in; every exponential after the first runs
  *                    in place on psi_out.
  * Synchronises the stream once (the energy range).  QW_ENOCONV if more than
@@ -175,8 +175,8 @@ qw_status qw_bessel_j(double a, int mmax, double *J);
 
 /* Workspace bytes for one action call on n qubits at precision 64 (complex64
  * state, float diagonal) or 128 (complex128, double diagonal).  on_the_fly != 0
- * sizes the variant that never stores the diagonal (diag == NULL, n >= 31 or
- * forced by the flag of the action call). */
+ * sizes the variant that never stores the diagonal (complex64 with diag == NULL
+ * and n >= 31). */
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly);
 
 /* Shift c and bound r of H - cI (section II.A): c = (max E + min E)/2,
@@ -199,8 +199,10 @@ qw_status qw_spectral_bound_f64(int n, const double *diag, const double *h, cons
  *   n       : 1..32.
  *   diag    : device, N energies (float for _c64, double for _c128), or NULL to
  *             generate them from h, J (host arrays as in qw_spectral_bound_*).
- *             With diag == NULL and n >= 31 the diagonal is recomputed inside
- *             every Clenshaw term from per-tile tables and never stored.
+ *             With diag == NULL and n >= 31 the complex64 call recomputes the
+ *             diagonal inside every Clenshaw term from per-tile tables and never
+ *             stores it; complex128 stores it in the workspace (n = 32: the
+ *             workspace is 172 GB, with psi 240 GB in all).
  *   psi_in  : device, N complex values; psi_out: device, N complex values; they
  *             may be the same buffer.
  *   tol     : truncation tolerance (absolute, for a unit-norm psi).

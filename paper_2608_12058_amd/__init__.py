@@ -178,7 +178,7 @@ def spectral_bound(n: int, gamma: float, diag=None, h=None, J=None, precision: i
     """(c, r): shift and induced 1-norm bound of H - cI."""
     torch = _torch()
     if workspace is None:
-        workspace = Workspace.for_problem(n, precision, diag is None and n >= 31)
+        workspace = Workspace.for_problem(n, precision, diag is None and n >= 31 and precision == 64)
     _, hp = _host_f64(h, n) if diag is None else (None, None)
     _, Jp = _host_f64(J, n * (n - 1) // 2) if diag is None else (None, None)
     if diag is not None:
@@ -229,7 +229,7 @@ def expm_action(psi, gamma: float, t: float, *, diag=None, h=None, J=None, tol: 
             raise ValueError("give diag, or h and J")
         _h, hp = _host_f64(h, n)
         _J, Jp = _host_f64(J, n * (n - 1) // 2)
-    otf = diag is None and n >= 31
+    otf = diag is None and n >= 31 and prec == 64
     if workspace is None:
         workspace = Workspace.for_problem(n, prec, otf, device=psi.device)
     info = QwInfo()
@@ -289,7 +289,7 @@ def poly_action(psi, coef, gamma: float, *, basis: str = "cheb", diag=None, h=No
             raise ValueError("give diag, or h and J")
         _h, hp = _host_f64(h, n)
         _J, Jp = _host_f64(J, n * (n - 1) // 2)
-    otf = diag is None and n >= 31
+    otf = diag is None and n >= 31 and prec == 64
     if workspace is None:
         workspace = Workspace.for_problem(n, prec, otf, device=psi.device)
     c = 0.0 if shift is None else float(shift)
@@ -339,7 +339,7 @@ def anneal_cfet4(psi, h, J, A, B, T: float, *, steps: int = 0, tol: float = 1e-6
     elif out.dtype != psi.dtype or out.numel() != N or not out.is_contiguous():
         raise ValueError("out must match psi")
     if workspace is None:
-        workspace = Workspace.for_problem(n, prec, n >= 31, device=psi.device)
+        workspace = Workspace.for_problem(n, prec, n >= 31 and prec == 64, device=psi.device)
     rec = np.zeros(max(1, int(max_record)), dtype=np.float64)
     info = CfetInfo()
     info.timing = int(timing)

@@ -8,7 +8,8 @@
 //
 // Device layout: psi, b1, b2 are interleaved complex vectors of N = 2^n
 // amplitudes (bit j of the index = qubit j); the normalised diagonal
-// d = (E - c)/r is a real vector of N (or recomputed per tile for n >= 31).
+// d = (E - c)/r is a real vector of N (recomputed per tile instead in complex64
+// for n >= 31, where storing it would crowd the 288 GB).
 //
 // Per Clenshaw term the state is streamed in P passes (P = 1 for n <= 13 in
 // complex64): the first pass loads a contiguous tile of 2^13 amplitudes of
@@ -365,8 +366,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     using V = CVec<R>;
     qw_status st = validate<R>(n, diag, h, J, gamma, t, psi_in, psi_out, tol, method, workspace);
     if (st != QW_OK) return st;
-    const bool otf = (diag == nullptr && n >= 31);
-    if (otf && sizeof(R) != 4) { set_error("the on-the-fly diagonal is implemented for complex64 only"); return QW_EINVAL; }
+    const bool otf = (diag == nullptr && n >= 31 && sizeof(R) == 4);
     const WsLayout L = ws_layout(n, prec_of<R>(), otf);
     if (ws_bytes < L.total) {
         set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
@@ -640,7 +640,7 @@ static qw_status bound_entry(int n, const R *diag, const double *h, const double
 {
     if (n < 1 || n > 32 || !c || !r || !workspace || !finite(gamma)) { set_error("bad arguments"); return QW_EINVAL; }
     if (!diag && (!h || (n > 1 && !J))) { set_error("diag == NULL requires h and J"); return QW_EINVAL; }
-    const WsLayout L = ws_layout(n, prec_of<R>(), diag == nullptr && n >= 31);
+    const WsLayout L = ws_layout(n, prec_of<R>(), diag == nullptr && n >= 31 && sizeof(R) == 4);
     if (ws_bytes < L.total) { set_error("workspace too small"); return QW_ENOMEM; }
     EnergyTables T{};
     return bound_impl<R>(n, diag, h, J, gamma, static_cast<char *>(workspace), L,
@@ -701,7 +701,7 @@ qw_status prepare_energy(int n, const double *h, const double *J, void *workspac
                          EnergyTables *T, double *emin, double *emax)
 {
     if (n < 1 || n > 32 || !h || (n > 1 && !J) || !workspace) { set_error("bad arguments"); return QW_EINVAL; }
-    const WsLayout L = ws_layout(n, prec_of<R>(), n >= 31);
+    const WsLayout L = ws_layout(n, prec_of<R>(), n >= 31 && sizeof(R) == 4);
     if (ws_bytes < L.total) {
         set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
         return QW_ENOMEM;

@@ -121,3 +121,33 @@ def test_n32_time_reversal(env):
     assert err < 2e-5
     del y, x
     torch.cuda.empty_cache()
+
+
+def test_n32_c64_on_the_fly_matches_c128_stored(env):
+    """SK seed 0, gamma = 1, t = 0.3 from |+> at 32 qubits: the complex64 call
+    (diagonal recomputed per tile and term) against the complex128 call
+    (diagonal stored as doubles) on 4096 sampled amplitudes.  The complex64
+    buffers are released before the complex128 run, which holds psi (68.7 GB)
+    and its workspace (172 GB) at once."""
+    torch, qw = env
+    h, J = synth.sk_instance(N32, 0)
+    rng = np.random.default_rng(34)
+    idx = np.concatenate([[0, (1 << N32) - 1], rng.integers(0, 1 << N32, 4094)])
+    tidx = torch.as_tensor(idx, device="cuda")
+    x = synth.plus_state_torch(N32, "cuda", torch.complex64)
+    y, i64 = qw.expm_action(x, 1.0, 0.3, h=h, J=J, out=x)
+    got64 = y[tidx].cpu().numpy().astype(np.complex128)
+    del y, x
+    torch.cuda.empty_cache()
+    assert qw.workspace_bytes(N32, 128, False) < 180e9
+    x = synth.plus_state_torch(N32, "cuda", torch.complex128)
+    y, i128 = qw.expm_action(x, 1.0, 0.3, h=h, J=J, tol=1e-12, out=x)
+    got128 = y[tidx].cpu().numpy()
+    nrm = torch.linalg.vector_norm(y).item()
+    del y, x
+    torch.cuda.empty_cache()
+    # 2^14-amplitude complex64 tiles: 14 + 9 + 9 bits; 2^12-amplitude complex128
+    # tiles: 12 + 9 + 9 + 2 bits
+    assert i64["passes"] == 3 and i128["passes"] == 4
+    assert abs(nrm - 1.0) < 1e-11
+    assert rel(got64, got128) <= 1e-5
