@@ -249,6 +249,13 @@ template <bool STREAM, typename T> __device__ __forceinline__ T ld_s(const T *p)
     else return *p;
 }
 
+// a * b + c rounded once (v_fma_f32 / v_fma_f64)
+template <typename R> __device__ __forceinline__ R fmad(R a, R b, R c)
+{
+    if constexpr (sizeof(R) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
 template <typename R> struct PassArgs {
     using C = typename Cplx<R>::T;
     const C *b1;   // b_{k+1}: its flips over the tile's group are summed
@@ -378,10 +385,17 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     }
 
     V own[PER], accv[PER];
-    // psi is prefetched before the barrier, except with the on-the-fly diagonal,
-    // whose extra registers would then spill: there it is read where it is used
-    constexpr bool EARLY_PSI = DIAG && !OTF;
+    // Every load of the tile is issued before the first barrier where the
+    // registers allow it (requests issued later, between the LDS phases, left
+    // HBM idle: loading acc after the barrier cost 4-12 % per pass).  START
+    // prefetches psi; FUSED prefetches the diagonal and reads psi where it is
+    // used, since psi, d, b_{k+1} and the partial b_k together would exceed the
+    // 128 registers of four waves per SIMD.  With the on-the-fly diagonal psi is
+    // read where it is used.
+    constexpr bool EARLY_PSI = DIAG && !OTF && MODE != PM_FUSED;
+    constexpr bool EARLY_D = (MODE == PM_FUSED) && !OTF;
     V psiv[EARLY_PSI ? PER : 1];
+    R dv[EARLY_D ? PER : 1][VE];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
@@ -395,6 +409,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                 for (int v = 0; v < VE; ++v) accv[q].v[v] = C{R(0), R(0)};
             }
             if constexpr (EARLY_PSI) psiv[q] = ld_v<R, STREAM>(a.psi + idx);
+            if constexpr (EARLY_D) {
+#pragma unroll
+                for (int v = 0; v < VE; ++v) dv[q][v] = ld_s<STREAM>(a.d + idx + v);
+            }
 #pragma unroll
             for (int v = 0; v < VE; ++v) lds[e + v] = own[q].v[v];
         }
@@ -436,9 +454,9 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
             for (int j = 0; j < a.h; ++j) step(j);
         }
     };
-    // Diagonal of element ee (global index idx): loaded from d (after the
-    // barrier, to keep it out of the registers held across it) or rebuilt from
-    // the tile fields.  Rebuilt, the linear part sum_j s_j f_j splits by the
+    // Diagonal of element ee (global index idx) for START: loaded from d (after
+    // the barrier, to keep it out of the registers held across it) or rebuilt
+    // from the tile fields (also in FUSED).  Rebuilt, the linear part sum_j s_j f_j splits by the
     // bits of ee = (q NT + thread) VE + v: the thread's bits give one partial
     // sum per thread (tpart), so each element adds only its q bits and bit 0.
     constexpr int LOG_NT = (NT >= 1024) ? 10 : (NT >= 512) ? 9 : (NT >= 256) ? 8 : 7;
@@ -460,9 +478,23 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
         }
     };
 
+    // Element arithmetic with explicit fused multiply-adds, so that the START
+    // pass and the second half of FUSED (which compute the same first part of
+    // a term) round identically whatever the compiler would contract: the
+    // gradient's recomputed windows rely on it.
+    //   first part:  scale (d b + g F b) - sub s + c psi
+    //   completion:  acc + sg F b
+    auto first_part = [&](R dd, const C &b, R sr, R si, const C &sb, const C &ps, R scale) -> C {
+        const R hr = fmad(dd, b.x, a.g * sr), hi = fmad(dd, b.y, a.g * si);
+        const R tr = fmad(scale, hr, -(a.sub * sb.x)), ti = fmad(scale, hi, -(a.sub * sb.y));
+        const R ur = fmad(a.cr, ps.x, -(a.ci * ps.y)), ui = fmad(a.cr, ps.y, a.ci * ps.x);
+        return C{tr + ur, ti + ui};
+    };
+
     double nrm = 0.0;
     if constexpr (MODE == PM_FUSED) {
-        // complete b_k in registers
+        // complete b_k in registers and store it at once (stored at the end of
+        // the pass beside b_{k-1}, the stores bunched up: 1-2 % slower)
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
@@ -472,9 +504,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                 const R sg = a.scale * a.g;
 #pragma unroll
                 for (int v = 0; v < VE; ++v) {
-                    accv[q].v[v].x += sg * sr[v];
-                    accv[q].v[v].y += sg * si[v];
+                    accv[q].v[v].x = fmad(sg, sr[v], accv[q].v[v].x);
+                    accv[q].v[v].y = fmad(sg, si[v], accv[q].v[v].y);
                 }
+                st_v<R, STREAM>(a.dst + tile_index(base, e, a.L, a.g0), accv[q]);
             }
         }
         __syncthreads();   // every flip of b_{k+1} has been read
@@ -497,16 +530,14 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                 flips(e, accv[q], sr, si);
 #pragma unroll
                 for (int v = 0; v < VE; ++v) {
-                    const R dd = diag_of(idx + v, e + v);
+                    R dd;
+                    if constexpr (EARLY_D) dd = dv[q][v] * a.dscale;
+                    else dd = diag_of(idx + v, e + v);
                     const C bk = accv[q].v[v], bp = own[q].v[v];
                     const C ps = EARLY_PSI ? psiv[q].v[v] : a.psi[idx + v];
-                    const R hr = dd * bk.x + a.g * sr[v];
-                    const R hi = dd * bk.y + a.g * si[v];
-                    out.v[v].x = (a.scale2 * hr - a.sub * bp.x) + (a.cr * ps.x - a.ci * ps.y);
-                    out.v[v].y = (a.scale2 * hi - a.sub * bp.y) + (a.cr * ps.y + a.ci * ps.x);
+                    out.v[v] = first_part(dd, bk, sr[v], si[v], bp, ps, a.scale2);
                     if (a.norm_acc) nrm += (double)bk.x * bk.x + (double)bk.y * bk.y;
                 }
-                st_v<R, STREAM>(a.dst + idx, accv[q]);
                 st_v<R, STREAM>(a.dst2 + idx, out);
             }
         }
@@ -526,20 +557,17 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                     C o;
                     if constexpr (MODE == PM_START) {
                         const R dd = diag_of(idx + v, ee);
-                        const C b = own[q].v[v], ac = accv[q].v[v];
                         const C ps = EARLY_PSI ? psiv[q].v[v] : a.psi[idx + v];
-                        const R hr = dd * b.x + a.g * sr;
-                        const R hi = dd * b.y + a.g * si;
-                        o.x = (a.scale * hr - a.sub * ac.x) + (a.cr * ps.x - a.ci * ps.y);
-                        o.y = (a.scale * hi - a.sub * ac.y) + (a.cr * ps.y + a.ci * ps.x);
+                        o = first_part(dd, own[q].v[v], sr, si, accv[q].v[v], ps, a.scale);
                     } else {
                         const C ac = accv[q].v[v];
                         const R sg = a.scale * a.g;
-                        o.x = ac.x + sg * sr;
-                        o.y = ac.y + sg * si;
+                        o.x = fmad(sg, sr, ac.x);
+                        o.y = fmad(sg, si, ac.y);
                     }
-                    out.v[v].x = a.pr * o.x - a.pi * o.y;
-                    out.v[v].y = a.pr * o.y + a.pi * o.x;
+                    // times pr + i pi; exact for 1 + 0i
+                    out.v[v].x = fmad(a.pr, o.x, -(a.pi * o.y));
+                    out.v[v].y = fmad(a.pr, o.y, a.pi * o.x);
                     if (a.norm_acc) nrm += (double)out.v[v].x * out.v[v].x + (double)out.v[v].y * out.v[v].y;
                 }
                 st_v<R, STREAM>(a.dst + idx, out);
