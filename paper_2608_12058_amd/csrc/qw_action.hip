@@ -215,8 +215,14 @@ static void launch_pass(const PassArgs<R> &a, int mode, bool otf, uint64_t ntile
             if (cfg.stream) return launch_shape<R, TB_WIDE, NT_WIDE, true, true>(a, mode, otf, ntiles, s);
             return launch_shape<R, TB_WIDE, NT_WIDE, true, false>(a, mode, otf, ntiles, s);
         }
-        if (cfg.tb == TB_NARROW) return launch_shape<R, TB_NARROW, NT_NARROW, false, false>(a, mode, otf, ntiles, s);
-        if (cfg.nt == NT_MID) return launch_shape<R, Cfg<R>::TB, NT_MID, false, false>(a, mode, otf, ntiles, s);
+        if (cfg.tb == TB_NARROW) {
+            if (cfg.stream) return launch_shape<R, TB_NARROW, NT_NARROW, false, true>(a, mode, otf, ntiles, s);
+            return launch_shape<R, TB_NARROW, NT_NARROW, false, false>(a, mode, otf, ntiles, s);
+        }
+        if (cfg.nt == NT_MID) {
+            if (cfg.stream) return launch_shape<R, Cfg<R>::TB, NT_MID, false, true>(a, mode, otf, ntiles, s);
+            return launch_shape<R, Cfg<R>::TB, NT_MID, false, false>(a, mode, otf, ntiles, s);
+        }
         if (cfg.stream) return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, true, true>(a, mode, otf, ntiles, s);
         return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, true, false>(a, mode, otf, ntiles, s);
     } else {
@@ -485,7 +491,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     const bool horner = poly && poly->horner;
     const TileCfg cfg = tile_cfg_for<R>(n);
     const int tb = cfg.tb;
-    const std::vector<PassPlan> plan = plan_passes(n, tb, Cfg<R>::LMIN);
+    const std::vector<PassPlan> plan = plan_passes(n, tb, Cfg<R>::LMIN, cfg.tb0);
     if (info) {
         info->K = K;
         info->a = a;
@@ -609,19 +615,13 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         pa.cr = (R)cr;
         pa.ci = (R)ci;
         const uint64_t ntiles = N >> (pl.L + pl.h);
-        // the streaming hint pays on the strided passes (rows gathered from far
-        // apart) of every shape; on the contiguous first orientation it pays
-        // with the wide complex64 tiles and in complex128, but not with the
-        // default complex64 tiles (measured per term at 28 qubits: 3544 us with
-        // the hint on every pass, 3415 us without it on the contiguous pass)
-        // XCD-major tile order for the default complex64 tiles, except on the
-        // orientation of the top bits (measured per term at 28 qubits: 3415 us
-        // in launch order, 3393 XCD-major everywhere, 3374 everywhere but the
-        // top orientation; no gain in complex128 or with wide tiles)
+        // XCD-major tile order for the default (and split) complex64 tiles,
+        // except on the orientation of the top bits (measured per term at 28
+        // qubits: 3415 us in launch order, 3393 XCD-major everywhere, 3374
+        // everywhere but the top orientation; no gain in complex128 or with
+        // wide tiles)
         pa.xcd_order = (sizeof(R) == 4 && cfg.tb == Cfg<R>::TB && cfg.nt == Cfg<R>::NT && pl.g0 + pl.h < n) ? 1 : 0;
-        TileCfg pcfg = cfg;
-        pcfg.stream = cfg.stream && (pl.L > 0 || !(sizeof(R) == 4 && cfg.tb == Cfg<R>::TB));
-        launch_pass<R>(pa, sp.mode, otf, ntiles, s, pcfg);
+        launch_pass<R>(pa, sp.mode, otf, ntiles, s, pass_cfg<R>(cfg, pl, sp.mode));
         ptimer.mark(sp.orient);
         if (sp.mode == PM_FUSED || (sp.mode == PM_START && P == 1)) std::swap(X, Y);
     }
@@ -653,7 +653,8 @@ static qw_status bound_entry(int n, const R *diag, const double *h, const double
 int check_plan(int n, int prec)
 {
     const int TB = (prec == 64) ? tile_cfg_for<float>(n).tb : tile_cfg_for<double>(n).tb;
-    std::vector<PassPlan> plan = plan_passes(n, TB, (prec == 64) ? Cfg<float>::LMIN : Cfg<double>::LMIN);
+    const int TB0 = (prec == 64) ? tile_cfg_for<float>(n).tb0 : tile_cfg_for<double>(n).tb0;
+    std::vector<PassPlan> plan = plan_passes(n, TB, (prec == 64) ? Cfg<float>::LMIN : Cfg<double>::LMIN, TB0);
     const uint64_t N = uint64_t(1) << n;
     int covered_bits = 0;
     for (const PassPlan &p : plan) {
@@ -751,7 +752,7 @@ using namespace qw;
 extern "C" {
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.6 (gfx950, fused passes, tile shapes, XCD order)"; }
+const char *qw_version(void) { return "qwexp 0.7 (gfx950, fused passes, split tiles, XCD order)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {

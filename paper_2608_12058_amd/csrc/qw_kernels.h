@@ -388,12 +388,16 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     // Every load of the tile is issued before the first barrier where the
     // registers allow it (requests issued later, between the LDS phases, left
     // HBM idle: loading acc after the barrier cost 4-12 % per pass).  START
-    // prefetches psi; FUSED prefetches the diagonal and reads psi where it is
-    // used, since psi, d, b_{k+1} and the partial b_k together would exceed the
-    // 128 registers of four waves per SIMD.  With the on-the-fly diagonal psi is
-    // read where it is used.
-    constexpr bool EARLY_PSI = DIAG && !OTF && MODE != PM_FUSED;
-    constexpr bool EARLY_D = (MODE == PM_FUSED) && !OTF;
+    // prefetches psi.  Complex64 FUSED prefetches the diagonal and reads psi
+    // where it is used, since psi, d, b_{k+1} and the partial b_k together would
+    // exceed the 128 registers of four waves per SIMD, and stores b_k as soon as
+    // it is complete (together: 1.5 % per term at 28 qubits); complex128 FUSED
+    // prefetches psi, reads d where it is used and stores b_k beside b_{k-1}
+    // (the complex64 order made its contiguous pass 10 % slower).  With the
+    // on-the-fly diagonal psi is read where it is used.
+    constexpr bool C64 = sizeof(R) == 4;
+    constexpr bool EARLY_PSI = DIAG && !OTF && (MODE != PM_FUSED || !C64);
+    constexpr bool EARLY_D = (MODE == PM_FUSED) && !OTF && C64;
     V psiv[EARLY_PSI ? PER : 1];
     R dv[EARLY_D ? PER : 1][VE];
 #pragma unroll
@@ -493,8 +497,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
 
     double nrm = 0.0;
     if constexpr (MODE == PM_FUSED) {
-        // complete b_k in registers and store it at once (stored at the end of
-        // the pass beside b_{k-1}, the stores bunched up: 1-2 % slower)
+        // complete b_k in registers (complex64: and store it at once)
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
@@ -507,7 +510,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                     accv[q].v[v].x = fmad(sg, sr[v], accv[q].v[v].x);
                     accv[q].v[v].y = fmad(sg, si[v], accv[q].v[v].y);
                 }
-                st_v<R, STREAM>(a.dst + tile_index(base, e, a.L, a.g0), accv[q]);
+                if constexpr (C64) st_v<R, STREAM>(a.dst + tile_index(base, e, a.L, a.g0), accv[q]);
             }
         }
         __syncthreads();   // every flip of b_{k+1} has been read
@@ -527,6 +530,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                 const uint64_t idx = tile_index(base, e, a.L, a.g0);
                 V out;
                 R sr[VE], si[VE];
+                V psl;   // one 16-byte load, hinted as the pass
+                if constexpr (!EARLY_PSI) psl = ld_v<R, STREAM>(a.psi + idx);
                 flips(e, accv[q], sr, si);
 #pragma unroll
                 for (int v = 0; v < VE; ++v) {
@@ -534,10 +539,11 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                     if constexpr (EARLY_D) dd = dv[q][v] * a.dscale;
                     else dd = diag_of(idx + v, e + v);
                     const C bk = accv[q].v[v], bp = own[q].v[v];
-                    const C ps = EARLY_PSI ? psiv[q].v[v] : a.psi[idx + v];
+                    const C ps = EARLY_PSI ? psiv[q].v[v] : psl.v[v];
                     out.v[v] = first_part(dd, bk, sr[v], si[v], bp, ps, a.scale2);
                     if (a.norm_acc) nrm += (double)bk.x * bk.x + (double)bk.y * bk.y;
                 }
+                if constexpr (!C64) st_v<R, STREAM>(a.dst + idx, accv[q]);
                 st_v<R, STREAM>(a.dst2 + idx, out);
             }
         }
@@ -698,13 +704,13 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 struct PassPlan { int L, g0, h; };
 
 // Orientations of one Clenshaw term for tiles of 2^TB amplitudes: the first
-// takes the low min(n, TB) bits contiguously, the rest split the high bits as
-// evenly as possible into groups of at most TB - LMIN bits, each tile keeping
-// L = TB - h passenger bits for contiguous rows.
-inline std::vector<PassPlan> plan_passes(int n, int TB, int LMIN)
+// takes the low min(n, TB0) bits contiguously (TB0 = TB unless given), the rest
+// split the high bits as evenly as possible into groups of at most TB - LMIN
+// bits, each tile keeping L = TB - h passenger bits for contiguous rows.
+inline std::vector<PassPlan> plan_passes(int n, int TB, int LMIN, int TB0 = 0)
 {
     std::vector<PassPlan> P;
-    const int h0 = std::min(n, TB);
+    const int h0 = std::min(n, TB0 > 0 ? TB0 : TB);
     P.push_back({0, 0, h0});
     const int rem = n - h0;
     if (rem > 0) {
@@ -736,13 +742,22 @@ template <typename R> inline std::vector<PassPlan> plan_passes(int n)
 // threads.  Measured per term: n = 21 19.0 us with 1024 threads against 24.7
 // with 512; at n = 22 and n = 28 the 512-thread shape is faster (36.3 against
 // 38.4 us, 3.62 against 3.75 ms).
+// Split: complex64 25 <= n <= 28 takes its contiguous orientation on 2^12
+// tiles, and the high bits split into groups of at most 8 (rows of >= 256 B)
+// with the same pass count: at 28 qubits 12 + 8 + 8 bits instead of 13 + 8 + 7,
+// 3306 -> 3186 us per term (the contiguous fused pass 1095 -> 998 us, the add
+// pass 1114 -> 1077); 25, 26, 27 qubits: 405 -> 396, 818 -> 792, 1650 -> 1604 us.
+// From 29 qubits the high bits would need a group of 9 (128-byte rows) or one
+// more pass.
 static constexpr int TB_WIDE = 14, NT_WIDE = 1024;
 static constexpr int TB_NARROW = 12, NT_NARROW = 1024;
 static constexpr int NT_MID = 1024;   // complex64 2^13 tiles, 8 amplitudes per thread
+static constexpr int SPLIT_NMIN = 25, SPLIT_NMAX = 28;
 
 struct TileCfg {
     int tb, nt;
     bool stream;   // non-temporal accesses (vectors well beyond the memory-side cache)
+    int tb0 = 0;   // > 0: split shape, the contiguous orientation on 2^tb0 tiles
 };
 
 // Streaming pays once the call's vectors (b1, b2, psi, out and the diagonal)
@@ -759,6 +774,7 @@ template <typename R> inline TileCfg tile_cfg_for(int n)
     constexpr int TB = Cfg<R>::TB, LMIN = Cfg<R>::LMIN;
     const bool st = stream_for<R>(n);
     if constexpr (sizeof(R) == 4) {
+        if (n >= SPLIT_NMIN && n <= SPLIT_NMAX) return {TB, Cfg<R>::NT, st, TB_NARROW};
         if (n >= TB_WIDE + 9 && plan_passes(n, TB_WIDE, LMIN).size() < plan_passes(n, TB, LMIN).size())
             return {TB_WIDE, NT_WIDE, st};
         if (n > TB && n <= 20 && plan_passes(n, TB_NARROW, LMIN).size() == plan_passes(n, TB, LMIN).size())
@@ -768,6 +784,28 @@ template <typename R> inline TileCfg tile_cfg_for(int n)
         if (n > TB && n <= 21) return {TB_NARROW, NT_NARROW, false};
     }
     return {TB, Cfg<R>::NT, st};
+}
+
+// Launch shape of one pass of a call whose tiles are cfg.  Split shape: the
+// contiguous orientation runs on 2^tb0-amplitude tiles with 1024 threads (two
+// workgroups and 32 waves per CU instead of 16), the strided add passes on the
+// 2^13 tiles with 1024 threads (4 amplitudes each: 49 registers, 8 waves per
+// SIMD), the strided fused passes in the default shape; every pass streams.
+// Otherwise the streaming hint pays on the strided passes (rows gathered from
+// far apart) of every shape; on the contiguous first orientation it pays with
+// the wide complex64 tiles and in complex128, but not with the default complex64
+// tiles (measured per term at 28 qubits: 3544 us with the hint on every pass,
+// 3415 us without it on the contiguous pass).
+template <typename R> inline TileCfg pass_cfg(const TileCfg &cfg, const PassPlan &pl, int mode)
+{
+    if (cfg.tb0 > 0) {
+        if (pl.L == 0) return {cfg.tb0, NT_NARROW, cfg.stream};
+        if (mode == PM_ADD) return {cfg.tb, NT_MID, cfg.stream};
+        return {cfg.tb, cfg.nt, cfg.stream};
+    }
+    TileCfg p = cfg;
+    p.stream = cfg.stream && (pl.L > 0 || !(sizeof(R) == 4 && cfg.tb == Cfg<R>::TB));
+    return p;
 }
 
 #define QW_HIP(call)                                                                   \
