@@ -220,6 +220,23 @@ def test_n28_c64_matches_c128(env):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("n", [25, 26, 27])
+def test_split_shape_c64_matches_c128(env, n):
+    """25-27 qubits run complex64 on the split tile shape (contiguous orientation
+    on 2^12 tiles, 12 + groups of at most 8 bits) and complex128 on its default
+    2^12 tiles (12 + groups of at most 9): a random state through both."""
+    torch, qw = env
+    h, J = synth.sk_instance(n, 300 + n)
+    psi = torch.as_tensor(synth.random_state(n, 400 + n)).cuda()
+    y128, i128 = qw.expm_action(psi, 0.9, 0.3, h=h, J=J, tol=1e-12)
+    y64, i64 = qw.expm_action(psi.to(torch.complex64), 0.9, 0.3, h=h, J=J, tol=2.0 ** -23)
+    assert i64["passes"] == 3
+    err = (torch.linalg.vector_norm(y64.to(torch.complex128) - y128) / torch.linalg.vector_norm(y128)).item()
+    assert err < C64_TOL
+    del y128, y64, psi
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("prec", [64, 128])
 def test_n28_sampled_closed_forms(env, oracle_mod, prec):
     """H_P = 0 on a random product state, and gamma = 0 on |+>, checked at 4096
