@@ -192,9 +192,18 @@ static qw_status bound_impl(int n, const R *diag, const double *h, const double 
 }
 
 template <typename R, int TB, int NT, bool WITH_OTF, bool STREAM>
-static void launch_shape(const PassArgs<R> &a, int mode, bool otf, uint64_t ntiles, hipStream_t s)
+static void launch_shape(const PassArgs<R> &a, int mode, bool otf, uint64_t ntiles, hipStream_t s,
+                         bool keep_pd = false)
 {
     const dim3 grid((unsigned)ntiles), block(NT);
+    if constexpr (STREAM && sizeof(R) == 4) {
+        if (keep_pd && !otf) {
+            if (mode == PM_START) hipLaunchKernelGGL((k_pass<R, TB, NT, PM_START, false, true, true>), grid, block, 0, s, a);
+            else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass<R, TB, NT, PM_FUSED, false, true, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_pass<R, TB, NT, PM_ADD, false, true, true>), grid, block, 0, s, a);
+            return;
+        }
+    }
     if constexpr (WITH_OTF) {
         if (otf && mode == PM_START) { hipLaunchKernelGGL((k_pass<R, TB, NT, PM_START, true, STREAM>), grid, block, 0, s, a); return; }
         if (otf && mode == PM_FUSED) { hipLaunchKernelGGL((k_pass<R, TB, NT, PM_FUSED, true, STREAM>), grid, block, 0, s, a); return; }
@@ -211,19 +220,20 @@ template <typename R>
 static void launch_pass(const PassArgs<R> &a, int mode, bool otf, uint64_t ntiles, hipStream_t s, TileCfg cfg)
 {
     if constexpr (sizeof(R) == 4) {
+        const bool kp = cfg.keep_pd;
         if (cfg.tb == TB_WIDE) {
-            if (cfg.stream) return launch_shape<R, TB_WIDE, NT_WIDE, true, true>(a, mode, otf, ntiles, s);
+            if (cfg.stream) return launch_shape<R, TB_WIDE, NT_WIDE, true, true>(a, mode, otf, ntiles, s, kp);
             return launch_shape<R, TB_WIDE, NT_WIDE, true, false>(a, mode, otf, ntiles, s);
         }
         if (cfg.tb == TB_NARROW) {
-            if (cfg.stream) return launch_shape<R, TB_NARROW, NT_NARROW, false, true>(a, mode, otf, ntiles, s);
+            if (cfg.stream) return launch_shape<R, TB_NARROW, NT_NARROW, false, true>(a, mode, otf, ntiles, s, kp);
             return launch_shape<R, TB_NARROW, NT_NARROW, false, false>(a, mode, otf, ntiles, s);
         }
         if (cfg.nt == NT_MID) {
-            if (cfg.stream) return launch_shape<R, Cfg<R>::TB, NT_MID, false, true>(a, mode, otf, ntiles, s);
+            if (cfg.stream) return launch_shape<R, Cfg<R>::TB, NT_MID, false, true>(a, mode, otf, ntiles, s, kp);
             return launch_shape<R, Cfg<R>::TB, NT_MID, false, false>(a, mode, otf, ntiles, s);
         }
-        if (cfg.stream) return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, true, true>(a, mode, otf, ntiles, s);
+        if (cfg.stream) return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, true, true>(a, mode, otf, ntiles, s, kp);
         return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, true, false>(a, mode, otf, ntiles, s);
     } else {
         if (cfg.nt == NT_NARROW) return launch_shape<R, TB_NARROW, NT_NARROW, false, false>(a, mode, otf, ntiles, s);

@@ -220,7 +220,11 @@ enum PassMode { PM_START = 0, PM_ADD = 1, PM_FUSED = 2 };
 // reads and writes each amplitude once and nothing is reused from the caches
 // (measured at 28 qubits: 6 % faster in complex64, 10 % in complex128); when
 // they fit, the hint costs the reuse between passes (10-15 % slower at 20
-// qubits), so small calls and the batched form run without it.
+// qubits), so small calls and the batched form run without it.  KEEP_PD (with
+// STREAM) leaves psi and the diagonal unhinted: while those two (12 B per
+// amplitude in complex64) stay within about twice the cache, they are re-read
+// from it every term as the b vectors stream past (24 qubits: 152.9 -> 140.6 us
+// per term; 25: 395 -> 383; 26: no change; 28: 3186 -> 3204).
 typedef float qw_f4 __attribute__((ext_vector_type(4)));
 template <typename R, bool STREAM> __device__ __forceinline__ CVec<R> ld_v(const typename Cplx<R>::T *p)
 {
@@ -361,7 +365,7 @@ __global__ void k_qtable_orient(const double *hJ, int n, int L, int g0, int h, d
 // The Clenshaw recurrence uses scale 2 (1 on the final step) and sub 1; Horner's
 // rule (y_k = H y_{k+1} + a_k psi) the same passes with scale 1 and sub 0.
 // FUSED needs b_k of the whole tile, so the tile is re-staged through LDS.
-template <typename R, int TB, int NT, int MODE, bool OTF, bool STREAM = false>
+template <typename R, int TB, int NT, int MODE, bool OTF, bool STREAM = false, bool KEEP_PD = false>
 __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, typename Cplx<R>::T *lds)
 {
     using C = typename Cplx<R>::T;
@@ -396,6 +400,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     // (the complex64 order made its contiguous pass 10 % slower).  With the
     // on-the-fly diagonal psi is read where it is used.
     constexpr bool C64 = sizeof(R) == 4;
+    constexpr bool PD_HINT = STREAM && !KEEP_PD;   // hint on the psi and diagonal loads
     constexpr bool EARLY_PSI = DIAG && !OTF && (MODE != PM_FUSED || !C64);
     constexpr bool EARLY_D = (MODE == PM_FUSED) && !OTF && C64;
     V psiv[EARLY_PSI ? PER : 1];
@@ -412,10 +417,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
 #pragma unroll
                 for (int v = 0; v < VE; ++v) accv[q].v[v] = C{R(0), R(0)};
             }
-            if constexpr (EARLY_PSI) psiv[q] = ld_v<R, STREAM>(a.psi + idx);
+            if constexpr (EARLY_PSI) psiv[q] = ld_v<R, PD_HINT>(a.psi + idx);
             if constexpr (EARLY_D) {
 #pragma unroll
-                for (int v = 0; v < VE; ++v) dv[q][v] = ld_s<STREAM>(a.d + idx + v);
+                for (int v = 0; v < VE; ++v) dv[q][v] = ld_s<PD_HINT>(a.d + idx + v);
             }
 #pragma unroll
             for (int v = 0; v < VE; ++v) lds[e + v] = own[q].v[v];
@@ -478,7 +483,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
             s += (ee & 1) ? -fld[0] : fld[0];
             return (R)s;
         } else {
-            return ld_s<STREAM>(a.d + idx) * a.dscale;
+            return ld_s<PD_HINT>(a.d + idx) * a.dscale;
         }
     };
 
@@ -531,7 +536,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                 V out;
                 R sr[VE], si[VE];
                 V psl;   // one 16-byte load, hinted as the pass
-                if constexpr (!EARLY_PSI) psl = ld_v<R, STREAM>(a.psi + idx);
+                if constexpr (!EARLY_PSI) psl = ld_v<R, PD_HINT>(a.psi + idx);
                 flips(e, accv[q], sr, si);
 #pragma unroll
                 for (int v = 0; v < VE; ++v) {
@@ -585,12 +590,12 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
 
 // Two 512-thread workgroups share a CU (64 KB of LDS each): registers are
 // capped so that both fit (4 waves per SIMD).
-template <typename R, int TB, int NT, int MODE, bool OTF, bool STREAM = false>
+template <typename R, int TB, int NT, int MODE, bool OTF, bool STREAM = false, bool KEEP_PD = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_pass(PassArgs<R> a)
 {
     __shared__ typename Cplx<R>::T lds[1 << TB];
     const uint64_t tile = a.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
-    pass_tile<R, TB, NT, MODE, OTF, STREAM>(a, tile, lds);
+    pass_tile<R, TB, NT, MODE, OTF, STREAM, KEEP_PD>(a, tile, lds);
 }
 
 // Whole recurrence of one small instance (n <= TB) inside one workgroup.
@@ -756,8 +761,9 @@ static constexpr int SPLIT_NMIN = 25, SPLIT_NMAX = 28;
 
 struct TileCfg {
     int tb, nt;
-    bool stream;   // non-temporal accesses (vectors well beyond the memory-side cache)
-    int tb0 = 0;   // > 0: split shape, the contiguous orientation on 2^tb0 tiles
+    bool stream;           // non-temporal accesses (vectors well beyond the memory-side cache)
+    int tb0 = 0;           // > 0: split shape, the contiguous orientation on 2^tb0 tiles
+    bool keep_pd = false;  // with stream: psi and the diagonal loaded without the hint
 };
 
 // Streaming pays once the call's vectors (b1, b2, psi, out and the diagonal)
@@ -769,7 +775,7 @@ template <typename R> inline bool stream_for(int n)
     return std::ldexp(per_amp, n) > 384.0 * (1 << 20);
 }
 
-template <typename R> inline TileCfg tile_cfg_for(int n)
+template <typename R> inline TileCfg tile_cfg_for_shape(int n)
 {
     constexpr int TB = Cfg<R>::TB, LMIN = Cfg<R>::LMIN;
     const bool st = stream_for<R>(n);
@@ -786,6 +792,15 @@ template <typename R> inline TileCfg tile_cfg_for(int n)
     return {TB, Cfg<R>::NT, st};
 }
 
+// Complex64 keeps psi and the diagonal cacheable while they take at most
+// 384 MB (n <= 25).
+template <typename R> inline TileCfg tile_cfg_for(int n)
+{
+    TileCfg c = tile_cfg_for_shape<R>(n);
+    c.keep_pd = c.stream && sizeof(R) == 4 && std::ldexp(12.0, n) <= 384.0 * (1 << 20);
+    return c;
+}
+
 // Launch shape of one pass of a call whose tiles are cfg.  Split shape: the
 // contiguous orientation runs on 2^tb0-amplitude tiles with 1024 threads (two
 // workgroups and 32 waves per CU instead of 16), the strided add passes on the
@@ -799,9 +814,9 @@ template <typename R> inline TileCfg tile_cfg_for(int n)
 template <typename R> inline TileCfg pass_cfg(const TileCfg &cfg, const PassPlan &pl, int mode)
 {
     if (cfg.tb0 > 0) {
-        if (pl.L == 0) return {cfg.tb0, NT_NARROW, cfg.stream};
-        if (mode == PM_ADD) return {cfg.tb, NT_MID, cfg.stream};
-        return {cfg.tb, cfg.nt, cfg.stream};
+        if (pl.L == 0) return {cfg.tb0, NT_NARROW, cfg.stream, 0, cfg.keep_pd};
+        if (mode == PM_ADD) return {cfg.tb, NT_MID, cfg.stream, 0, cfg.keep_pd};
+        return {cfg.tb, cfg.nt, cfg.stream, 0, cfg.keep_pd};
     }
     TileCfg p = cfg;
     p.stream = cfg.stream && (pl.L > 0 || !(sizeof(R) == 4 && cfg.tb == Cfg<R>::TB));
