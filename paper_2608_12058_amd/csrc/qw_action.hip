@@ -196,7 +196,7 @@ static void launch_shape(const PassArgs<R> &a, int mode, bool otf, uint64_t ntil
                          bool keep_pd = false)
 {
     const dim3 grid((unsigned)ntiles), block(NT);
-    if constexpr (STREAM && sizeof(R) == 4) {
+    if constexpr (STREAM) {
         if (keep_pd && !otf) {
             if (mode == PM_START) hipLaunchKernelGGL((k_pass<R, TB, NT, PM_START, false, true, true>), grid, block, 0, s, a);
             else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass<R, TB, NT, PM_FUSED, false, true, true>), grid, block, 0, s, a);
@@ -237,7 +237,7 @@ static void launch_pass(const PassArgs<R> &a, int mode, bool otf, uint64_t ntile
         return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, true, false>(a, mode, otf, ntiles, s);
     } else {
         if (cfg.nt == NT_NARROW) return launch_shape<R, TB_NARROW, NT_NARROW, false, false>(a, mode, otf, ntiles, s);
-        if (cfg.stream) return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, false, true>(a, mode, otf, ntiles, s);
+        if (cfg.stream) return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, false, true>(a, mode, otf, ntiles, s, cfg.keep_pd);
         return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, false, false>(a, mode, otf, ntiles, s);
     }
 }

@@ -222,9 +222,10 @@ enum PassMode { PM_START = 0, PM_ADD = 1, PM_FUSED = 2 };
 // they fit, the hint costs the reuse between passes (10-15 % slower at 20
 // qubits), so small calls and the batched form run without it.  KEEP_PD (with
 // STREAM) leaves psi and the diagonal unhinted: while those two (12 B per
-// amplitude in complex64) stay within about twice the cache, they are re-read
-// from it every term as the b vectors stream past (24 qubits: 152.9 -> 140.6 us
-// per term; 25: 395 -> 383; 26: no change; 28: 3186 -> 3204).
+// amplitude in complex64, 24 in complex128) take at most 384 MB, they are
+// re-read from the cache every term as the b vectors stream past (complex64 24
+// qubits: 152.9 -> 140.6 us per term, 25: 395 -> 383, 26: no change, 28: 3186
+// -> 3204; complex128 23 qubits: 230.4 -> 207.8, 24: 421.9 -> 415.5).
 typedef float qw_f4 __attribute__((ext_vector_type(4)));
 template <typename R, bool STREAM> __device__ __forceinline__ CVec<R> ld_v(const typename Cplx<R>::T *p)
 {
@@ -792,12 +793,12 @@ template <typename R> inline TileCfg tile_cfg_for_shape(int n)
     return {TB, Cfg<R>::NT, st};
 }
 
-// Complex64 keeps psi and the diagonal cacheable while they take at most
-// 384 MB (n <= 25).
+// psi and the diagonal stay cacheable while they take at most 384 MB
+// (complex64 n <= 25, complex128 n <= 24).
 template <typename R> inline TileCfg tile_cfg_for(int n)
 {
     TileCfg c = tile_cfg_for_shape<R>(n);
-    c.keep_pd = c.stream && sizeof(R) == 4 && std::ldexp(12.0, n) <= 384.0 * (1 << 20);
+    c.keep_pd = c.stream && std::ldexp(sizeof(R) == 4 ? 12.0 : 24.0, n) <= 384.0 * (1 << 20);
     return c;
 }
 
