@@ -30,7 +30,7 @@ METRIC = "n=28 exp(-itH)ψ: amps·terms/s, HBM GB/s % peak; fp32/batched/grad vs
 UNIT = "amps·terms/s"
 PEAK_HBM_GBPS = 8000.0
 BYTES_PER_AMP_TERM = {64: 36, 128: 72}     # algorithmic bytes per amplitude and term
-BYTES_INIT = {64: 24, 128: 48}             # b_K = c_K psi, b_{K+1} = 0
+BYTES_INIT = {64: 0, 128: 0}               # b_K = c_K psi is read by the first term's passes
 
 
 def parse():

@@ -565,8 +565,12 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         }
     }
     timer.mark(1);
-    {
-        // b_K = c_K psi (b_{K+1} = 0 is never read: the first pass takes acc = NULL)
+    // Clenshaw start b_K = c_K psi (b_{K+1} = 0 is never read: the first pass
+    // takes acc = NULL).  With several orientations the passes of term K-1 read
+    // psi and scale it as they load it, so b_K is never stored; with one
+    // orientation it is stored, since term K-2 reads it again as b_{k+2}.
+    const bool fuse_start = (P >= 2);
+    if (!fuse_start) {
         const double cr = cre[K], ci = cim[K];
         hipLaunchKernelGGL(k_scale<R>, dim3(eg), dim3(256), 0, s, reinterpret_cast<const V *>(psi),
                            reinterpret_cast<V *>(X), (R)cr, (R)ci, nvec);
@@ -586,6 +590,14 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         const PassPlan &pl = plan[sp.orient];
         double cr = 0.0, ci = 0.0;
         pa.b1 = X;
+        pa.b1_scaled = 0;
+        if (fuse_start && sp.k == K - 1) {
+            // b_{k+1} = b_K = c_K psi; X is free and takes the FUSED pass's dst2
+            pa.b1 = psi;
+            pa.b1_scaled = 1;
+            pa.b1r = (R)cre[K];
+            pa.b1i = (R)cim[K];
+        }
         pa.L = pl.L;
         pa.g0 = pl.g0;
         pa.h = pl.h;
@@ -625,12 +637,13 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         pa.cr = (R)cr;
         pa.ci = (R)ci;
         const uint64_t ntiles = N >> (pl.L + pl.h);
-        // XCD-major tile order for the default (and split) complex64 tiles,
+        // XCD-major tile order for the default, split and wide complex64 tiles,
         // except on the orientation of the top bits (measured per term at 28
         // qubits: 3415 us in launch order, 3393 XCD-major everywhere, 3374
-        // everywhere but the top orientation; no gain in complex128 or with
-        // wide tiles)
-        pa.xcd_order = (sizeof(R) == 4 && cfg.tb == Cfg<R>::TB && cfg.nt == Cfg<R>::NT && pl.g0 + pl.h < n) ? 1 : 0;
+        // everywhere but the top orientation; wide tiles at 32 qubits: 2127 ->
+        // 2090 ms for 38 terms; no gain in complex128)
+        const bool xcd_shape = (cfg.tb == Cfg<R>::TB && cfg.nt == Cfg<R>::NT) || cfg.tb == TB_WIDE;
+        pa.xcd_order = (sizeof(R) == 4 && xcd_shape && pl.g0 + pl.h < n) ? 1 : 0;
         launch_pass<R>(pa, sp.mode, otf, ntiles, s, pass_cfg<R>(cfg, pl, sp.mode));
         ptimer.mark(sp.orient);
         if (sp.mode == PM_FUSED || (sp.mode == PM_START && P == 1)) std::swap(X, Y);
@@ -762,7 +775,7 @@ using namespace qw;
 extern "C" {
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.7 (gfx950, fused passes, split tiles, XCD order)"; }
+const char *qw_version(void) { return "qwexp 0.8 (gfx950, fused passes, split tiles, fused start)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {

@@ -281,6 +281,8 @@ template <typename R> struct PassArgs {
     int n, L, g0, h;
     double *norm_acc = nullptr;   // if set: += sum |b|^2 of the completed vector (atomic, one per block)
     int xcd_order = 0;            // 1: blocks take tiles in XCD-major order (xcd_tile)
+    int b1_scaled = 0;            // 1: b1 points at psi and b_{k+1} = (b1r + i b1i) psi (the
+    R b1r = R(1), b1i = R(0);     //    Clenshaw start b_K = c_K psi, never stored)
 };
 
 // Workgroups of a launch are dealt round-robin to the 8 XCDs (block b on XCD
@@ -412,6 +414,13 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
         if (e < TE) {
             const uint64_t idx = tile_index(base, e, a.L, a.g0);
             own[q] = ld_v<R, STREAM>(a.b1 + idx);
+            if (a.b1_scaled) {
+#pragma unroll
+                for (int v = 0; v < VE; ++v) {
+                    const C p = own[q].v[v];
+                    own[q].v[v] = C{fmad(a.b1r, p.x, -(a.b1i * p.y)), fmad(a.b1r, p.y, a.b1i * p.x)};
+                }
+            }
             if (a.acc) {
                 accv[q] = ld_v<R, STREAM>(a.acc + idx);
             } else {
