@@ -156,10 +156,14 @@ __global__ void __launch_bounds__(256) k_init_batched(const BatchDesc *D, const 
 // host launches the fused and the final instances of a step separately.
 // 1024 threads per workgroup (16 waves, one workgroup per CU): the per-instance
 // arguments live in vector registers here, so fewer amplitudes per thread keep
-// the fused pass free of spills.
+// the fused pass free of spills (capped at 64 registers for two workgroups per
+// CU it spilled and ran 6 % slower).  STREAM: the b vectors carry the
+// non-temporal hint and psi and the diagonal stay cacheable, for waves whose
+// vectors exceed the memory-side cache (256 instances of 12..22 qubits, 7.7 GB:
+// 1093 -> 1020 ms; the hint on psi and the diagonal as well: 1043 ms).
 static constexpr int BNT = 1024;
 
-template <bool HIGH, int MODE>
+template <bool HIGH, int MODE, bool STREAM = false>
 __global__ void __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(4)))
 k_pass_batched(const BatchDesc *D, const int2 *tiles, int step)
 {
@@ -212,7 +216,7 @@ k_pass_batched(const BatchDesc *D, const int2 *tiles, int step)
         a.cr = ck.x;
         a.ci = ck.y;
     }
-    pass_tile<float, TB, NT, MODE, false>(a, (uint64_t)tt.y, lds);
+    pass_tile<float, TB, NT, MODE, false, STREAM, STREAM>(a, (uint64_t)tt.y, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -507,17 +511,20 @@ static qw_status batched_impl(const qw_batch_item *items, int count, const doubl
     std::vector<int2> tiles;
     tiles.reserve(P.n_tiles);
     // prefix[j]: tiles of the instances still active at step j (K >= j)
-    struct WaveSched { int tile_begin; std::vector<int> prefix; };
+    struct WaveSched { int tile_begin; std::vector<int> prefix; bool stream; };
     std::vector<WaveSched> sched;
     for (auto &w : waves) {
         std::sort(w.begin(), w.end(), [&](int a, int b) { return run.K[a] > run.K[b]; });
-        WaveSched ws_{(int)tiles.size(), {}};
+        WaveSched ws_{(int)tiles.size(), {}, false};
         std::vector<int> cum;
+        double wave_vec_bytes = 0.0;   // b1, b2, psi, out (8 B each) and the diagonal per amplitude
         for (int i : w) {
+            wave_vec_bytes += std::ldexp(36.0, items[i].n);
             const int nt = 1 << (items[i].n - Cfg<float>::TB);
             for (int t = 0; t < nt; ++t) tiles.push_back(make_int2(i, t));
             cum.push_back((int)tiles.size() - ws_.tile_begin);
         }
+        ws_.stream = wave_vec_bytes > 384.0 * (1 << 20);
         const int maxK = run.K[w.front()];
         ws_.prefix.resize(maxK + 1);
         size_t j = w.size();
@@ -556,11 +563,19 @@ static qw_status batched_impl(const qw_batch_item *items, int count, const doubl
                 const dim3 g(count), bl(BNT);
                 const int2 *t0 = wt + begin;
                 const BatchDesc *dd = dD;
-                if (mode == PM_START) hipLaunchKernelGGL((k_pass_batched<false, PM_START>), g, bl, 0, s, dd, t0, st);
-                else if (mode == PM_FUSED && high) hipLaunchKernelGGL((k_pass_batched<true, PM_FUSED>), g, bl, 0, s, dd, t0, st);
-                else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass_batched<false, PM_FUSED>), g, bl, 0, s, dd, t0, st);
-                else if (high) hipLaunchKernelGGL((k_pass_batched<true, PM_ADD>), g, bl, 0, s, dd, t0, st);
-                else hipLaunchKernelGGL((k_pass_batched<false, PM_ADD>), g, bl, 0, s, dd, t0, st);
+                if (w.stream) {
+                    if (mode == PM_START) hipLaunchKernelGGL((k_pass_batched<false, PM_START, true>), g, bl, 0, s, dd, t0, st);
+                    else if (mode == PM_FUSED && high) hipLaunchKernelGGL((k_pass_batched<true, PM_FUSED, true>), g, bl, 0, s, dd, t0, st);
+                    else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass_batched<false, PM_FUSED, true>), g, bl, 0, s, dd, t0, st);
+                    else if (high) hipLaunchKernelGGL((k_pass_batched<true, PM_ADD, true>), g, bl, 0, s, dd, t0, st);
+                    else hipLaunchKernelGGL((k_pass_batched<false, PM_ADD, true>), g, bl, 0, s, dd, t0, st);
+                } else {
+                    if (mode == PM_START) hipLaunchKernelGGL((k_pass_batched<false, PM_START>), g, bl, 0, s, dd, t0, st);
+                    else if (mode == PM_FUSED && high) hipLaunchKernelGGL((k_pass_batched<true, PM_FUSED>), g, bl, 0, s, dd, t0, st);
+                    else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass_batched<false, PM_FUSED>), g, bl, 0, s, dd, t0, st);
+                    else if (high) hipLaunchKernelGGL((k_pass_batched<true, PM_ADD>), g, bl, 0, s, dd, t0, st);
+                    else hipLaunchKernelGGL((k_pass_batched<false, PM_ADD>), g, bl, 0, s, dd, t0, st);
+                }
                 run.launches++;
             };
             for (int st = 0; st <= last; ++st) {
