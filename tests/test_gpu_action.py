@@ -4,8 +4,8 @@ Element-by-element comparisons (relative L2 over the whole vector) at sizes the
 oracle finishes in seconds, spanning the on-chip path (n <= 13) and every tile
 shape of the multi-pass path: 2^12-amplitude tiles with 1024 threads (n <= 20 in
 complex64, <= 21 in complex128), 2^13 tiles with 1024 threads (n = 21) and 512
-threads (n = 22, and three orientations from n = 25), 2^14 tiles (n = 23, 24);
-at the full 28-qubit
+threads (n = 22), 2^14 tiles (n = 23, 24), the split shape of three orientations
+(n = 25..28: 2^12 tiles on the contiguous one); at the full 28-qubit
 workload, properties that hold at any size and closed forms evaluated one
 sampled amplitude at a time.
 
@@ -127,6 +127,24 @@ def test_in_place(env, oracle_mod, prec, n):
     ref = oracle_mod.expm_action(n, E, 1.0, 0.7, psi, 1e-13)
     y, _ = _run(env, n, psi, 1.0, 0.7, 1e-12 if prec == 128 else 2.0 ** -23, prec, h=h, J=J, inplace=True)
     assert rel(y, ref) <= (C64_TOL if prec == 64 else C128_TOL)
+
+
+@pytest.mark.parametrize("prec,n", [(64, 16), (128, 16), (128, 22), (64, 25)])
+@pytest.mark.parametrize("a", [1e-4, 1e-2, 0.3])
+def test_low_degree_in_place(env, oracle_mod, prec, n, a):
+    """Degrees 1..10, where every pass of the call belongs to the first term or
+    two (whose b_{k+1} is psi scaled by c_K as the passes load it), with the
+    output written over the input: two and three orientations."""
+    torch, qw = env
+    h, J = synth.sk_instance(n, 50 + n)
+    E = oracle_mod.energies(n, h, J)
+    _, r = oracle_mod.spectral_shift_radius(E, n, 0.8)
+    psi = synth.random_state(n, 60 + n)
+    tol = 1e-6 if prec == 64 else 1e-12
+    y, info = _run(env, n, psi, 0.8, a / r, tol, prec, h=h, J=J, inplace=True)
+    assert 1 <= info["K"] <= 10 and info["passes"] >= 2, info
+    ref = oracle_mod.expm_action(n, E, 0.8, a / r, psi, 1e-13)
+    assert rel(y, ref) <= (C64_TOL if prec == 64 else C128_TOL), info
 
 
 @pytest.mark.parametrize("prec", [64, 128])
