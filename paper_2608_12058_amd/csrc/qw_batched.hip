@@ -163,6 +163,13 @@ __global__ void __launch_bounds__(256) k_init_batched(const BatchDesc *D, const 
 // 1093 -> 1020 ms; the hint on psi and the diagonal as well: 1043 ms).
 static constexpr int BNT = 1024;
 
+// c_k of an instance, read through a global pointer (one value for the block)
+__device__ __forceinline__ float2 coef_at(const float2 *coef, int k)
+{
+    const QW_GLOBAL float *c = (const QW_GLOBAL float *)(coef + k);
+    return make_float2(c[0], c[1]);
+}
+
 template <bool HIGH, int MODE, bool STREAM = false>
 __global__ void __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(4)))
 k_pass_batched(const BatchDesc *D, const int2 *tiles, int step)
@@ -193,7 +200,7 @@ k_pass_batched(const BatchDesc *D, const int2 *tiles, int step)
     }
     if constexpr (MODE == PM_START) {
         const int k = b.K - 1;
-        const float2 ck = b.coef[k];
+        const float2 ck = coef_at(b.coef, k);
         a.acc = nullptr;
         a.dst = Y;
         a.scale = (k == 0) ? 1.f : 2.f;
@@ -207,7 +214,7 @@ k_pass_batched(const BatchDesc *D, const int2 *tiles, int step)
         a.pi = b.pi;
     } else {
         const int k = b.K - step;   // completed here; k - 1 is started
-        const float2 ck = b.coef[k - 1];
+        const float2 ck = coef_at(b.coef, k - 1);
         a.acc = Y;
         a.dst = Y;
         a.dst2 = X;

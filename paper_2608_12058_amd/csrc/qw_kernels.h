@@ -227,31 +227,35 @@ enum PassMode { PM_START = 0, PM_ADD = 1, PM_FUSED = 2 };
 // qubits: 152.9 -> 140.6 us per term, 25: 395 -> 383, 26: no change, 28: 3186
 // -> 3204; complex128 23 qubits: 230.4 -> 207.8, 24: 421.9 -> 415.5).
 typedef float qw_f4 __attribute__((ext_vector_type(4)));
+// Every access goes through a global-address-space pointer: the passes touch
+// device memory only, and pointers that reach a kernel through a descriptor in
+// memory (the batched form) would otherwise be accessed with flat instructions,
+// which take 64-bit vector addresses and are counted with the LDS operations
+// (every LDS wait would then also wait for the loads in flight).
+#define QW_GLOBAL __attribute__((address_space(1)))
 template <typename R, bool STREAM> __device__ __forceinline__ CVec<R> ld_v(const typename Cplx<R>::T *p)
 {
-    if constexpr (STREAM) {
-        const qw_f4 x = __builtin_nontemporal_load(reinterpret_cast<const qw_f4 *>(p));
-        CVec<R> r;
-        __builtin_memcpy(&r, &x, sizeof(r));
-        return r;
-    } else {
-        return *reinterpret_cast<const CVec<R> *>(p);
-    }
+    const QW_GLOBAL qw_f4 *g = (const QW_GLOBAL qw_f4 *)p;
+    qw_f4 x;
+    if constexpr (STREAM) x = __builtin_nontemporal_load(g);
+    else x = *g;
+    CVec<R> r;
+    __builtin_memcpy(&r, &x, sizeof(r));
+    return r;
 }
 template <typename R, bool STREAM> __device__ __forceinline__ void st_v(typename Cplx<R>::T *p, const CVec<R> &v)
 {
-    if constexpr (STREAM) {
-        qw_f4 x;
-        __builtin_memcpy(&x, &v, sizeof(x));
-        __builtin_nontemporal_store(x, reinterpret_cast<qw_f4 *>(p));
-    } else {
-        *reinterpret_cast<CVec<R> *>(p) = v;
-    }
+    QW_GLOBAL qw_f4 *g = (QW_GLOBAL qw_f4 *)p;
+    qw_f4 x;
+    __builtin_memcpy(&x, &v, sizeof(x));
+    if constexpr (STREAM) __builtin_nontemporal_store(x, g);
+    else *g = x;
 }
 template <bool STREAM, typename T> __device__ __forceinline__ T ld_s(const T *p)
 {
-    if constexpr (STREAM) return __builtin_nontemporal_load(p);
-    else return *p;
+    const QW_GLOBAL T *g = (const QW_GLOBAL T *)p;
+    if constexpr (STREAM) return __builtin_nontemporal_load(g);
+    else return *g;
 }
 
 // a * b + c rounded once (v_fma_f32 / v_fma_f64)
