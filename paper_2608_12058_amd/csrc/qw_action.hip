@@ -775,7 +775,7 @@ using namespace qw;
 extern "C" {
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.8 (gfx950, fused passes, split tiles, fused start)"; }
+const char *qw_version(void) { return "qwexp 0.9 (gfx950, fused passes, split tiles, fused start)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {
