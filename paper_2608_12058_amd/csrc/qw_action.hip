@@ -556,8 +556,17 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     const int P = (int)plan.size();
     if (otf) {
         for (int o = 0; o < P; ++o) {
-            hipLaunchKernelGGL(k_qtable_orient<0>, dim3((1 << tb) / 256), dim3(256), 0, s, T.h, n, plan[o].L,
-                               plan[o].g0, plan[o].h, norm_inv_r, qt + (size_t)o * (1 << TB_WIDE));
+            // the on-the-fly shapes (default 2^13 tiles with 512 threads, wide 2^14
+            // with 1024) fill every tile: the split pair table needs L + h = TB
+            const TileCfg pc = pass_cfg<R>(cfg, plan[o], PM_FUSED);
+            const int log_nt = (pc.nt == 1024) ? 10 : 9;
+            if (plan[o].L + plan[o].h != pc.tb || (pc.nt != 1024 && pc.nt != 512) || pc.tb - log_nt > QS_MAX_R) {
+                set_error("internal: on-the-fly tile shape");
+                return QW_EINVAL;
+            }
+            hipLaunchKernelGGL(k_qsplit_orient<0>, dim3(((1 << log_nt) + 255) / 256), dim3(256), 0, s, T.h, n,
+                               plan[o].L, plan[o].g0, plan[o].h, log_nt, norm_inv_r,
+                               qt + (size_t)o * (1 << TB_WIDE));
             const uint64_t nt = N >> (plan[o].L + plan[o].h);
             hipLaunchKernelGGL(k_tile_fields<0>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, T.h, n,
                                plan[o].L, plan[o].g0, plan[o].h, nt, norm_c, norm_inv_r,

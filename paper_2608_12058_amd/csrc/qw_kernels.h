@@ -273,7 +273,7 @@ template <typename R> struct PassArgs {
     C *dst2;       // FUSED: the partial b_{k-1} (may alias b1)
     const C *psi;  // START, FUSED: v
     const R *d;    // START, FUSED: normalised diagonal (unless on the fly)
-    const float *Qt;   // on the fly: Q / r table of this orientation (2^(L+h) entries)
+    const float *Qt;   // on the fly: split pair tables of this orientation (k_qsplit_orient)
     const float *Ft;   // on the fly: per tile, f_i / r (i < L + h) and (C - c) / r at TILE_FIELDS - 1
     R dscale = R(1);   // the diagonal used is d * dscale
     R g;           // gamma / r
@@ -341,26 +341,44 @@ __global__ void __launch_bounds__(256) k_tile_fields(const double *hJ, int n, in
     out[TILE_FIELDS - 1] = (float)((C - c) * inv_r);
 }
 
-// Pair table of one orientation, scaled: Qt[e] = Q[e] / r in float.
+// Pair term of one orientation, split for a block of 2^LOG_NT threads.  Tile
+// element bits: T = bits 1..LOG_NT (the thread's), R = bit 0 and the bits above
+// T (the element's position among the thread's own).  With J'(a, b) the coupling
+// of the index bits of tile bits a, b divided by r,
+//   Q(e) = sum_{a<b} J'(a, b) s_a s_b = QTT(t) + sum_{j in R} s_j G_j(t) + QRR(r),
+//   G_j(t) = sum_{i in T} J'(i, j) s_i(t).
+// Written in float (sums in double): QTT[t] at QS_TT, the cross couplings
+// X[j * LOG_NT + i] = J'(T_i, R_j) at QS_X and QRR[r] at QS_RR, per orientation.
+static constexpr int QS_TT = 0, QS_X = 1024, QS_RR = 1152, QS_MAX_R = 8;
+
 template <int D = 0>
-__global__ void k_qtable_orient(const double *hJ, int n, int L, int g0, int h, double inv_r, float *Qt)
+__global__ void __launch_bounds__(256) k_qsplit_orient(const double *hJ, int n, int L, int g0, int h, int log_nt,
+                                                       double inv_r, float *Qs)
 {
-    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nv = L + h;
-    if (e >= (1u << nv)) return;
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
     const double *J = hJ + n;
-    double acc = 0.0;
-    for (int i = 0; i < nv; ++i) {
-        const int vi = (i < L) ? i : g0 + (i - L);
-        double fi = 0.0;
-        for (int j = i + 1; j < nv; ++j) {
-            const int vj = (j < L) ? j : g0 + (j - L);
-            const double Jij = J[pair_off(n, vi, vj)];
-            fi += ((e >> j) & 1) ? -Jij : Jij;
-        }
-        acc += ((e >> i) & 1) ? -fi : fi;
+    const int nv = L + h, nr = nv - log_nt;
+    auto vb = [&](int i) { return (i < L) ? i : g0 + (i - L); };
+    auto Jp = [&](int a, int b) {
+        const int x = vb(a), y = vb(b);
+        return J[pair_off(n, x < y ? x : y, x < y ? y : x)] * inv_r;
+    };
+    auto rbit = [&](int j) { return (j == 0) ? 0 : log_nt + j; };
+    if (u < (1 << log_nt)) {
+        double q = 0.0;
+        for (int a = 0; a < log_nt; ++a)
+            for (int b = a + 1; b < log_nt; ++b)
+                q += ((((u >> a) ^ (u >> b)) & 1) ? -1.0 : 1.0) * Jp(1 + a, 1 + b);
+        Qs[QS_TT + u] = (float)q;
     }
-    Qt[e] = (float)(acc * inv_r);
+    if (u < nr * log_nt) Qs[QS_X + u] = (float)Jp(1 + u % log_nt, rbit(u / log_nt));
+    if (u < (1 << nr)) {
+        double q = 0.0;
+        for (int a = 0; a < nr; ++a)
+            for (int b = a + 1; b < nr; ++b)
+                q += ((((u >> a) ^ (u >> b)) & 1) ? -1.0 : 1.0) * Jp(rbit(a), rbit(b));
+        Qs[QS_RR + u] = (float)q;
+    }
 }
 
 // One pass over one tile (see tile_base/tile_index); F_group sums the flips of
@@ -477,25 +495,44 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
             for (int j = 0; j < a.h; ++j) step(j);
         }
     };
-    // Diagonal of element ee (global index idx) for START: loaded from d (after
-    // the barrier, to keep it out of the registers held across it) or rebuilt
-    // from the tile fields (also in FUSED).  Rebuilt, the linear part sum_j s_j f_j splits by the
-    // bits of ee = (q NT + thread) VE + v: the thread's bits give one partial
-    // sum per thread (tpart), so each element adds only its q bits and bit 0.
+    // Diagonal of element (q, v) (global index idx) for START: loaded from d
+    // (after the barrier, to keep it out of the registers held across it) or
+    // rebuilt from the tile fields (also in FUSED).  Rebuilt: element bits ee =
+    // (q NT + thread) VE + v split into the thread's bits T and the rest R
+    // (v and the bits of q, r = v | q << 1, constants of the unrolled loops).
+    // With the tile fields f and the split pair term (k_qsplit_orient),
+    //   E/r = C' + sum_{i in T} s_i f_i + QTT(t) + sum_{j in R} s_j (f_j + G_j(t)) + QRR(r),
+    // so each thread forms base = C' + sum_T s_i f_i + QTT(t) and H_j = f_j + G_j(t)
+    // once, and an element adds its R signs of H_j and QRR(r).
     constexpr int LOG_NT = (NT >= 1024) ? 10 : (NT >= 512) ? 9 : (NT >= 256) ? 8 : 7;
     static_assert((1 << LOG_NT) == NT, "power-of-two block");
-    float tpart = 0.f;
+    constexpr int NR = OTF ? TB - LOG_NT : 1;   // the tile has TB bits (checked on the host)
+    static_assert(NR <= QS_MAX_R, "split pair table");
+    float base_t = 0.f, Hj[NR];
     if constexpr (OTF) {
         static_assert(VE == 2, "the on-the-fly diagonal is complex64 only");
-        for (int j = 0; j < LOG_NT; ++j)
-            if (1 + j < nv) tpart += ((threadIdx.x >> j) & 1) ? -fld[1 + j] : fld[1 + j];
+        const uint32_t t = threadIdx.x;
+        base_t = fbase + a.Qt[QS_TT + t];
+#pragma unroll
+        for (int i = 0; i < LOG_NT; ++i) base_t += ((t >> i) & 1) ? -fld[1 + i] : fld[1 + i];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            float g = fld[(j == 0) ? 0 : LOG_NT + j];
+#pragma unroll
+            for (int i = 0; i < LOG_NT; ++i) {
+                const float x = a.Qt[QS_X + j * LOG_NT + i];
+                g += ((t >> i) & 1) ? -x : x;
+            }
+            Hj[j] = g;
+        }
     }
-    auto diag_of = [&](uint64_t idx, uint32_t ee) -> R {
+    auto diag_of = [&](uint64_t idx, int q, int v) -> R {
         if constexpr (OTF) {
-            float s = fbase + a.Qt[ee] + tpart;
-            for (int j = 1 + LOG_NT; j < nv; ++j) s += ((ee >> j) & 1) ? -fld[j] : fld[j];
-            s += (ee & 1) ? -fld[0] : fld[0];
-            return (R)s;
+            const int r = v | (q << 1);
+            float s = base_t;
+#pragma unroll
+            for (int j = 0; j < NR; ++j) s += ((r >> j) & 1) ? -Hj[j] : Hj[j];
+            return (R)(s + a.Qt[QS_RR + r]);
         } else {
             return ld_s<PD_HINT>(a.d + idx) * a.dscale;
         }
@@ -556,7 +593,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                 for (int v = 0; v < VE; ++v) {
                     R dd;
                     if constexpr (EARLY_D) dd = dv[q][v] * a.dscale;
-                    else dd = diag_of(idx + v, e + v);
+                    else dd = diag_of(idx + v, q, v);
                     const C bk = accv[q].v[v], bp = own[q].v[v];
                     const C ps = EARLY_PSI ? psiv[q].v[v] : psl.v[v];
                     out.v[v] = first_part(dd, bk, sr[v], si[v], bp, ps, a.scale2);
@@ -577,11 +614,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                 flips(e, own[q], sr_, si_);
 #pragma unroll
                 for (int v = 0; v < VE; ++v) {
-                    const uint32_t ee = e + v;
                     const R sr = sr_[v], si = si_[v];
                     C o;
                     if constexpr (MODE == PM_START) {
-                        const R dd = diag_of(idx + v, ee);
+                        const R dd = diag_of(idx + v, q, v);
                         const C ps = EARLY_PSI ? psiv[q].v[v] : a.psi[idx + v];
                         o = first_part(dd, own[q].v[v], sr, si, accv[q].v[v], ps, a.scale);
                     } else {
