@@ -1,6 +1,7 @@
 """GPU tests of the norm monitor / caller-given bound (evaluation-error bound of
-section II.B.3, divergence status) and of the 32-qubit on-the-fly diagonal
-(sampled closed forms and time reversal at N = 2^32)."""
+section II.B.3, divergence status) and of the on-the-fly diagonal at 31 and 32
+qubits (sampled closed forms, time reversal, and complex64 against complex128
+with a stored diagonal)."""
 import numpy as np
 import pytest
 
@@ -73,23 +74,49 @@ def test_given_bound_matches_and_small_radius_diverges(env, oracle_mod, prec):
 N32 = 32
 
 
-def test_n32_gamma0_on_the_fly_diagonal(env, oracle_mod):
-    """gamma = 0 at 32 qubits: exp(-i t E(z)) on |+>, the diagonal recomputed
-    per tile and term; 512 sampled amplitudes against E(z) summed by its
-    definition for each sampled z."""
+@pytest.mark.parametrize("n", [31, 32])
+def test_n32_gamma0_on_the_fly_diagonal(env, oracle_mod, n):
+    """gamma = 0 at 31 and 32 qubits: exp(-i t E(z)) on |+>, the diagonal
+    recomputed per tile and term (31: 2^13-amplitude tiles with 512 threads,
+    13 + 9 + 9 bits; 32: 2^14 tiles with 1024 threads, 14 + 9 + 9); 512 sampled
+    amplitudes against E(z) summed by its definition for each sampled z."""
     torch, qw = env
-    h, J = synth.sk_instance(N32, 0)
-    psi = synth.plus_state_torch(N32, "cuda", torch.complex64)
+    h, J = synth.sk_instance(n, 0)
+    psi = synth.plus_state_torch(n, "cuda", torch.complex64)
     y, info = qw.expm_action(psi, 0.0, 1.0, h=h, J=J, out=psi)
-    assert info["passes"] == 3   # 2^14-amplitude tiles: 14 + 9 + 9 bits
-    rng = np.random.default_rng(32)
-    idx = np.concatenate([[0, (1 << N32) - 1], rng.integers(0, 1 << N32, 510)])
+    assert info["passes"] == 3
+    rng = np.random.default_rng(n)
+    idx = np.concatenate([[0, (1 << n) - 1], rng.integers(0, 1 << n, 510)])
     got = y[torch.as_tensor(idx, device="cuda")].cpu().numpy().astype(np.complex128)
-    amp = np.full(len(idx), 1.0 / np.sqrt(2.0 ** N32), dtype=np.complex128)
-    ref = oracle_mod.closed_form_gamma0_amps(N32, h, J, 1.0, amp, idx)
+    amp = np.full(len(idx), 1.0 / np.sqrt(2.0 ** n), dtype=np.complex128)
+    ref = oracle_mod.closed_form_gamma0_amps(n, h, J, 1.0, amp, idx)
     assert rel(got, ref) <= 1e-5
     del y, psi
     torch.cuda.empty_cache()
+
+
+def test_n31_c64_on_the_fly_matches_c128_stored(env):
+    """31 qubits, gamma = 1, t = 0.3 from |+>: complex64 with the diagonal
+    rebuilt per tile (default 2^13 tiles, 512 threads) against complex128 with
+    its stored diagonal, on 4096 sampled amplitudes."""
+    torch, qw = env
+    n = 31
+    h, J = synth.sk_instance(n, 1)
+    rng = np.random.default_rng(35)
+    idx = np.concatenate([[0, (1 << n) - 1], rng.integers(0, 1 << n, 4094)])
+    tidx = torch.as_tensor(idx, device="cuda")
+    x = synth.plus_state_torch(n, "cuda", torch.complex64)
+    y, i64 = qw.expm_action(x, 1.0, 0.3, h=h, J=J, out=x)
+    got64 = y[tidx].cpu().numpy().astype(np.complex128)
+    del y, x
+    torch.cuda.empty_cache()
+    x = synth.plus_state_torch(n, "cuda", torch.complex128)
+    y, i128 = qw.expm_action(x, 1.0, 0.3, h=h, J=J, tol=1e-12, out=x)
+    got128 = y[tidx].cpu().numpy()
+    del y, x
+    torch.cuda.empty_cache()
+    assert i64["passes"] == 3
+    assert rel(got64, got128) <= 1e-5
 
 
 def test_n32_hp0_product_state(env, oracle_mod):
