@@ -201,8 +201,10 @@ qw_status qw_spectral_bound_f64(int n, const double *diag, const double *h, cons
  *             generate them from h, J (host arrays as in qw_spectral_bound_*).
  *             With diag == NULL and n >= 31 the complex64 call recomputes the
  *             diagonal inside every Clenshaw term from per-tile tables and never
- *             stores it; complex128 stores it in the workspace (n = 32: the
- *             workspace is 172 GB, with psi 240 GB in all).
+ *             stores it (from 26 to 28 qubits only the pass of the top qubits
+ *             does, the others read the stored one); complex128 stores it in the
+ *             workspace (n = 32: the workspace is 172 GB, with psi 240 GB in
+ *             all).  A recomputed value is summed in double and rounded once.
  *   psi_in  : device, N complex values; psi_out: device, N complex values; they
  *             may be the same buffer.
  *   tol     : truncation tolerance (absolute, for a unit-norm psi).

@@ -85,9 +85,11 @@ static WsLayout ws_layout(int n, int prec, bool otf)
     L.red = take(2 * sizeof(double));
     L.hj = take((32 + 32 * 31 / 2) * sizeof(double));
     L.q = take((size_t(1) << LB_TAB) * sizeof(double));
-    L.qt = take(4 * (size_t(1) << TB_WIDE) * sizeof(float));   // one pair table per orientation
-    // on the fly: per-tile fields of every orientation (tiles of >= 2^13 amplitudes)
-    L.ft = otf ? take(4 * (N >> Cfg<float>::TB) * TILE_FIELDS * sizeof(float)) : size_t(-1);
+    L.qt = take(4 * (size_t(1) << TB_WIDE) * sizeof(double));   // split pair tables, per orientation
+    // on the fly (every orientation, or the top one of the split shape): per-tile
+    // fields, tiles of >= 2^12 amplitudes
+    const bool top = (prec == 64 && n >= OTF_TOP_NMIN && n <= SPLIT_NMAX);
+    L.ft = (otf || top) ? take(4 * (N >> TB_NARROW) * TILE_FIELDS * sizeof(double)) : size_t(-1);
     L.coef = (n <= Cfg<float>::TB) ? take((size_t)(KMAX_ONCHIP + 1) * cs) : size_t(-1);
     L.items = take(256);
     L.norms = take(KMAX_MON * sizeof(double));
@@ -226,7 +228,7 @@ static void launch_pass(const PassArgs<R> &a, int mode, bool otf, uint64_t ntile
             return launch_shape<R, TB_WIDE, NT_WIDE, true, false>(a, mode, otf, ntiles, s);
         }
         if (cfg.tb == TB_NARROW) {
-            if (cfg.stream) return launch_shape<R, TB_NARROW, NT_NARROW, false, true>(a, mode, otf, ntiles, s, kp);
+            if (cfg.stream) return launch_shape<R, TB_NARROW, NT_NARROW, true, true>(a, mode, otf, ntiles, s, kp);
             return launch_shape<R, TB_NARROW, NT_NARROW, false, false>(a, mode, otf, ntiles, s);
         }
         if (cfg.nt == NT_MID) {
@@ -382,7 +384,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     using V = CVec<R>;
     qw_status st = validate<R>(n, diag, h, J, gamma, t, psi_in, psi_out, tol, method, workspace);
     if (st != QW_OK) return st;
-    const bool otf = (diag == nullptr && n >= 31 && sizeof(R) == 4);
+    const bool otf = (diag == nullptr && n >= OTF_NMIN && sizeof(R) == 4);
     const WsLayout L = ws_layout(n, prec_of<R>(), otf);
     if (ws_bytes < L.total) {
         set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
@@ -464,9 +466,12 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     const double es = prep ? prep->escale : 1.0;
     const double norm_c = (es != 0.0) ? c / es : 0.0, norm_inv_r = es * inv_r;
     R *dn = otf ? nullptr : reinterpret_cast<R *>(ws + L.d);
-    float *qt = reinterpret_cast<float *>(ws + L.qt);
-    float *ft = otf ? reinterpret_cast<float *>(ws + L.ft) : nullptr;
-    const uint64_t ft_stride = (N >> Cfg<float>::TB) * TILE_FIELDS;   // floats per orientation
+    double *qt = reinterpret_cast<double *>(ws + L.qt);
+    // the top orientation of the split shape rebuilds the diagonal when it can
+    const bool otf_top = !otf && diag == nullptr && sizeof(R) == 4 && tile_cfg_for<R>(n).tb0 > 0 && n >= OTF_TOP_NMIN;
+    auto orient_otf = [&](const PassPlan &pl) { return otf || (otf_top && pl.L > 0 && pl.g0 + pl.h == n); };
+    double *ft = (otf || otf_top) ? reinterpret_cast<double *>(ws + L.ft) : nullptr;
+    const uint64_t ft_stride = (N >> TB_NARROW) * TILE_FIELDS;   // doubles per orientation
     if (!otf) {
         if (diag) {
             hipLaunchKernelGGL(k_normalize_diag<R>, dim3(grid_for(N, 256 * 8, 1 << 16)), dim3(256), 0, s,
@@ -554,8 +559,9 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
                            reinterpret_cast<const V *>(psi), nvec, norms + K + 1);
     }
     const int P = (int)plan.size();
-    if (otf) {
+    if (otf || otf_top) {
         for (int o = 0; o < P; ++o) {
+            if (!orient_otf(plan[o])) continue;
             // the on-the-fly shapes (default 2^13 tiles with 512 threads, wide 2^14
             // with 1024) fill every tile: the split pair table needs L + h = TB
             const TileCfg pc = pass_cfg<R>(cfg, plan[o], PM_FUSED);
@@ -611,7 +617,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         pa.g0 = pl.g0;
         pa.h = pl.h;
         pa.Qt = qt + (size_t)sp.orient * (1 << TB_WIDE);
-        pa.Ft = otf ? ft + (size_t)sp.orient * ft_stride : nullptr;
+        const bool pass_otf = orient_otf(pl);
+        pa.Ft = pass_otf ? ft + (size_t)sp.orient * ft_stride : nullptr;
         pa.pr = R(1);
         pa.pi = R(0);
         pa.dst2 = nullptr;
@@ -653,7 +660,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         // 2090 ms for 38 terms; no gain in complex128)
         const bool xcd_shape = (cfg.tb == Cfg<R>::TB && cfg.nt == Cfg<R>::NT) || cfg.tb == TB_WIDE;
         pa.xcd_order = (sizeof(R) == 4 && xcd_shape && pl.g0 + pl.h < n) ? 1 : 0;
-        launch_pass<R>(pa, sp.mode, otf, ntiles, s, pass_cfg<R>(cfg, pl, sp.mode));
+        launch_pass<R>(pa, sp.mode, pass_otf, ntiles, s, pass_cfg<R>(cfg, pl, sp.mode));
         ptimer.mark(sp.orient);
         if (sp.mode == PM_FUSED || (sp.mode == PM_START && P == 1)) std::swap(X, Y);
     }
@@ -672,7 +679,7 @@ static qw_status bound_entry(int n, const R *diag, const double *h, const double
 {
     if (n < 1 || n > 32 || !c || !r || !workspace || !finite(gamma)) { set_error("bad arguments"); return QW_EINVAL; }
     if (!diag && (!h || (n > 1 && !J))) { set_error("diag == NULL requires h and J"); return QW_EINVAL; }
-    const WsLayout L = ws_layout(n, prec_of<R>(), diag == nullptr && n >= 31 && sizeof(R) == 4);
+    const WsLayout L = ws_layout(n, prec_of<R>(), diag == nullptr && n >= OTF_NMIN && sizeof(R) == 4);
     if (ws_bytes < L.total) { set_error("workspace too small"); return QW_ENOMEM; }
     EnergyTables T{};
     return bound_impl<R>(n, diag, h, J, gamma, static_cast<char *>(workspace), L,
@@ -734,7 +741,7 @@ qw_status prepare_energy(int n, const double *h, const double *J, void *workspac
                          EnergyTables *T, double *emin, double *emax)
 {
     if (n < 1 || n > 32 || !h || (n > 1 && !J) || !workspace) { set_error("bad arguments"); return QW_EINVAL; }
-    const WsLayout L = ws_layout(n, prec_of<R>(), n >= 31 && sizeof(R) == 4);
+    const WsLayout L = ws_layout(n, prec_of<R>(), n >= OTF_NMIN && sizeof(R) == 4);
     if (ws_bytes < L.total) {
         set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
         return QW_ENOMEM;
@@ -784,7 +791,7 @@ using namespace qw;
 extern "C" {
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.9 (gfx950, fused passes, split tiles, fused start)"; }
+const char *qw_version(void) { return "qwexp 0.10 (gfx950, fused passes, split tiles, fused start, top-orientation diagonal on the fly)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {

@@ -273,8 +273,8 @@ template <typename R> struct PassArgs {
     C *dst2;       // FUSED: the partial b_{k-1} (may alias b1)
     const C *psi;  // START, FUSED: v
     const R *d;    // START, FUSED: normalised diagonal (unless on the fly)
-    const float *Qt;   // on the fly: split pair tables of this orientation (k_qsplit_orient)
-    const float *Ft;   // on the fly: per tile, f_i / r (i < L + h) and (C - c) / r at TILE_FIELDS - 1
+    const double *Qt;  // on the fly: split pair tables of this orientation (k_qsplit_orient)
+    const double *Ft;  // on the fly: per tile, f_i / r (i < L + h) and (C - c) / r at TILE_FIELDS - 1
     R dscale = R(1);   // the diagonal used is d * dscale
     R g;           // gamma / r
     R scale;       // START, ADD: 2 inside the recurrence, 1 for the final step; FUSED: for b_k
@@ -302,14 +302,14 @@ __device__ __forceinline__ uint64_t xcd_tile(uint32_t b, uint32_t nb)
 // the other index bits are fixed by the tile's base.  With
 //   f_i = h_vb(i) + sum_{u fixed} J_{vb(i) u} s_u,
 //   C   = sum_{u fixed} h_u s_u + sum_{u<w fixed} J_uw s_u s_w
-// and the orientation's pair table Q[e] = sum_{i<j} J_{vb(i) vb(j)} s_i(e) s_j(e),
+// and the orientation's pair term Q[e] = sum_{i<j} J_{vb(i) vb(j)} s_i(e) s_j(e),
 // E = C + Q[e] + sum_i f_i s_i(e).  One thread per tile writes f_i / r and
-// (C - c) / r in float (sums in double) to Ft[tile * TILE_FIELDS ...].
+// (C - c) / r in double to Ft[tile * TILE_FIELDS ...].
 static constexpr int TILE_FIELDS = 16;
 
 template <int D = 0>
 __global__ void __launch_bounds__(256) k_tile_fields(const double *hJ, int n, int L, int g0, int h, uint64_t ntiles,
-                                                     double c, double inv_r, float *Ft)
+                                                     double c, double inv_r, double *Ft)
 {
     const uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tile >= ntiles) return;
@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(256) k_tile_fields(const double *hJ, int n, in
     const uint64_t base = tile_base(tile, L, g0, h);
     auto isvar = [&](int u) { return u < L || (u >= g0 && u < g0 + h); };
     auto spin = [&](int u) { return ((base >> u) & 1) ? -1.0 : 1.0; };
-    float *out = Ft + tile * TILE_FIELDS;
+    double *out = Ft + tile * TILE_FIELDS;
     for (int i = 0; i < nv; ++i) {
         const int j = (i < L) ? i : g0 + (i - L);
         double acc = hh[j];
@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(256) k_tile_fields(const double *hJ, int n, in
             if (isvar(u)) continue;
             acc += spin(u) * J[pair_off(n, j < u ? j : u, j < u ? u : j)];
         }
-        out[i] = (float)(acc * inv_r);
+        out[i] = acc * inv_r;
     }
     double C = 0.0;
     for (int u = 0; u < n; ++u) {
@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(256) k_tile_fields(const double *hJ, int n, in
         }
         C += spin(u) * fu;
     }
-    out[TILE_FIELDS - 1] = (float)((C - c) * inv_r);
+    out[TILE_FIELDS - 1] = (C - c) * inv_r;
 }
 
 // Pair term of one orientation, split for a block of 2^LOG_NT threads.  Tile
@@ -347,13 +347,13 @@ __global__ void __launch_bounds__(256) k_tile_fields(const double *hJ, int n, in
 // of the index bits of tile bits a, b divided by r,
 //   Q(e) = sum_{a<b} J'(a, b) s_a s_b = QTT(t) + sum_{j in R} s_j G_j(t) + QRR(r),
 //   G_j(t) = sum_{i in T} J'(i, j) s_i(t).
-// Written in float (sums in double): QTT[t] at QS_TT, the cross couplings
-// X[j * LOG_NT + i] = J'(T_i, R_j) at QS_X and QRR[r] at QS_RR, per orientation.
+// Written in double: QTT[t] at QS_TT, the cross couplings X[j * LOG_NT + i] =
+// J'(T_i, R_j) at QS_X and QRR[r] at QS_RR, per orientation.
 static constexpr int QS_TT = 0, QS_X = 1024, QS_RR = 1152, QS_MAX_R = 8;
 
 template <int D = 0>
 __global__ void __launch_bounds__(256) k_qsplit_orient(const double *hJ, int n, int L, int g0, int h, int log_nt,
-                                                       double inv_r, float *Qs)
+                                                       double inv_r, double *Qs)
 {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     const double *J = hJ + n;
@@ -369,15 +369,15 @@ __global__ void __launch_bounds__(256) k_qsplit_orient(const double *hJ, int n, 
         for (int a = 0; a < log_nt; ++a)
             for (int b = a + 1; b < log_nt; ++b)
                 q += ((((u >> a) ^ (u >> b)) & 1) ? -1.0 : 1.0) * Jp(1 + a, 1 + b);
-        Qs[QS_TT + u] = (float)q;
+        Qs[QS_TT + u] = q;
     }
-    if (u < nr * log_nt) Qs[QS_X + u] = (float)Jp(1 + u % log_nt, rbit(u / log_nt));
+    if (u < nr * log_nt) Qs[QS_X + u] = Jp(1 + u % log_nt, rbit(u / log_nt));
     if (u < (1 << nr)) {
         double q = 0.0;
         for (int a = 0; a < nr; ++a)
             for (int b = a + 1; b < nr; ++b)
                 q += ((((u >> a) ^ (u >> b)) & 1) ? -1.0 : 1.0) * Jp(rbit(a), rbit(b));
-        Qs[QS_RR + u] = (float)q;
+        Qs[QS_RR + u] = q;
     }
 }
 
@@ -399,8 +399,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     constexpr int PER = (1 << TB) / (NT * VE);
     constexpr bool DIAG = (MODE != PM_ADD);
     static_assert(PER >= 1, "tile smaller than one vector per thread");
-    __shared__ float fld[OTF ? TB : 1];
-    __shared__ float fbase;
+    __shared__ double fld[OTF ? TB : 1];
+    __shared__ double fbase;
 
     const int nv = a.L + a.h;
     const uint32_t TE = 1u << nv;
@@ -408,7 +408,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
 
     if constexpr (OTF) {
         static_assert(TB < TILE_FIELDS, "tile fields and the constant fit one record");
-        const float *ft = a.Ft + tile * TILE_FIELDS;
+        const double *ft = a.Ft + tile * TILE_FIELDS;
         if ((int)threadIdx.x < nv) fld[threadIdx.x] = ft[threadIdx.x];
         if (threadIdx.x == 0) fbase = ft[TILE_FIELDS - 1];
     }
@@ -503,12 +503,13 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     // With the tile fields f and the split pair term (k_qsplit_orient),
     //   E/r = C' + sum_{i in T} s_i f_i + QTT(t) + sum_{j in R} s_j (f_j + G_j(t)) + QRR(r),
     // so each thread forms base = C' + sum_T s_i f_i + QTT(t) and H_j = f_j + G_j(t)
-    // once, and an element adds its R signs of H_j and QRR(r).
+    // once, and an element adds its R signs of H_j and QRR(r).  The sums run in
+    // double and are rounded to float once, as the stored diagonal is.
     constexpr int LOG_NT = (NT >= 1024) ? 10 : (NT >= 512) ? 9 : (NT >= 256) ? 8 : 7;
     static_assert((1 << LOG_NT) == NT, "power-of-two block");
     constexpr int NR = OTF ? TB - LOG_NT : 1;   // the tile has TB bits (checked on the host)
     static_assert(NR <= QS_MAX_R, "split pair table");
-    float base_t = 0.f, Hj[NR];
+    double base_t = 0.0, Hj[NR];
     if constexpr (OTF) {
         static_assert(VE == 2, "the on-the-fly diagonal is complex64 only");
         const uint32_t t = threadIdx.x;
@@ -517,10 +518,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
         for (int i = 0; i < LOG_NT; ++i) base_t += ((t >> i) & 1) ? -fld[1 + i] : fld[1 + i];
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
-            float g = fld[(j == 0) ? 0 : LOG_NT + j];
+            double g = fld[(j == 0) ? 0 : LOG_NT + j];
 #pragma unroll
             for (int i = 0; i < LOG_NT; ++i) {
-                const float x = a.Qt[QS_X + j * LOG_NT + i];
+                const double x = a.Qt[QS_X + j * LOG_NT + i];
                 g += ((t >> i) & 1) ? -x : x;
             }
             Hj[j] = g;
@@ -529,7 +530,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     auto diag_of = [&](uint64_t idx, int q, int v) -> R {
         if constexpr (OTF) {
             const int r = v | (q << 1);
-            float s = base_t;
+            double s = base_t;
 #pragma unroll
             for (int j = 0; j < NR; ++j) s += ((r >> j) & 1) ? -Hj[j] : Hj[j];
             return (R)(s + a.Qt[QS_RR + r]);
@@ -808,6 +809,15 @@ static constexpr int TB_WIDE = 14, NT_WIDE = 1024;
 static constexpr int TB_NARROW = 12, NT_NARROW = 1024;
 static constexpr int NT_MID = 1024;   // complex64 2^13 tiles, 8 amplitudes per thread
 static constexpr int SPLIT_NMIN = 25, SPLIT_NMAX = 28;
+// Complex64 calls without a caller diagonal rebuild it inside every term from
+// n = OTF_NMIN qubits on, where storing it would crowd the 288 GB; with the
+// split shape from OTF_TOP_NMIN qubits the fused pass of the top orientation
+// rebuilds it too (4 bytes per amplitude less there), the other passes read the
+// stored one.  Rebuilding costs per-thread set-up and double-precision sums,
+// which pay only on that pass (28 qubits, per term: contiguous fused pass 999 us
+// stored, 1095 rebuilt; top fused pass 1114 stored, 1023 rebuilt; 25 qubits,
+// where psi and the diagonal stay in the memory-side cache: 135 against 130).
+static constexpr int OTF_NMIN = 31, OTF_TOP_NMIN = 26;
 
 struct TileCfg {
     int tb, nt;
