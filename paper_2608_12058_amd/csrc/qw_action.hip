@@ -9,7 +9,8 @@
 // Device layout: psi, b1, b2 are interleaved complex vectors of N = 2^n
 // amplitudes (bit j of the index = qubit j); the normalised diagonal
 // d = (E - c)/r is a real vector of N (recomputed per tile instead in complex64
-// for n >= 31, where storing it would crowd the 288 GB).
+// for n >= 31, where storing it would crowd the 288 GB, and in the top
+// orientation's fused pass from 26 to 28 qubits).
 //
 // Per Clenshaw term the state is streamed in P passes (P = 1 for n <= 13 in
 // complex64): the first pass loads a contiguous tile of 2^13 amplitudes of
@@ -216,8 +217,9 @@ static void launch_shape(const PassArgs<R> &a, int mode, bool otf, uint64_t ntil
 }
 
 // Launches one pass in the tile shape chosen for the call (the on-the-fly
-// diagonal exists for the complex64 default and wide shapes, n >= 31; the
-// streaming hint for the shapes used at large n).
+// diagonal exists for the complex64 default and wide shapes: every fused pass
+// from 31 qubits, the top orientation's of the split shape; add passes never
+// read the diagonal; the streaming hint for the shapes used at large n).
 template <typename R>
 static void launch_pass(const PassArgs<R> &a, int mode, bool otf, uint64_t ntiles, hipStream_t s, TileCfg cfg)
 {
@@ -228,7 +230,7 @@ static void launch_pass(const PassArgs<R> &a, int mode, bool otf, uint64_t ntile
             return launch_shape<R, TB_WIDE, NT_WIDE, true, false>(a, mode, otf, ntiles, s);
         }
         if (cfg.tb == TB_NARROW) {
-            if (cfg.stream) return launch_shape<R, TB_NARROW, NT_NARROW, true, true>(a, mode, otf, ntiles, s, kp);
+            if (cfg.stream) return launch_shape<R, TB_NARROW, NT_NARROW, false, true>(a, mode, otf, ntiles, s, kp);
             return launch_shape<R, TB_NARROW, NT_NARROW, false, false>(a, mode, otf, ntiles, s);
         }
         if (cfg.nt == NT_MID) {
