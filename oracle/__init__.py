@@ -230,8 +230,9 @@ def clenshaw(n: int, c: np.ndarray, d: np.ndarray, g: float, v: np.ndarray,
     into b_k is done in place, as in sec. II.D.
 
     If ``norms`` is a list, (||b_k||, ||c_k v - b_{k+2}||, ||b_{k+1}||) is
-    appended for every step, the quantities of the evaluation-error bound
-    (sec. II.B.3)."""
+    appended for every step k = K, K-1, .., 0, the quantities of the
+    evaluation-error bound (sec. II.B.3); the step k = 0 forms the result y, so
+    its first entry is ||y||."""
     d = np.ascontiguousarray(d, dtype=np.float64)
     v = np.ascontiguousarray(v, dtype=np.complex128)
     K = len(c) - 1
@@ -253,9 +254,13 @@ def clenshaw(n: int, c: np.ndarray, d: np.ndarray, g: float, v: np.ndarray,
             norms.append((np.linalg.norm(b1), ck_v_minus_b2, nb1))
     y = np.empty_like(v)
     if norms is not None:
-        norms.append((0.0, np.linalg.norm(c[0] * v - b2), np.linalg.norm(b1)))
+        final = (np.linalg.norm(c[0] * v - b2), np.linalg.norm(b1))
     lib.orc_clenshaw_final(n, _p(d), float(g), float(c[0].real), float(c[0].imag),
                            _p(v), _p(b1), _p(b2), _p(y))
+    if norms is not None:
+        # the last step forms y = p(H) v in the place of b_0, so its rounding
+        # term is u ||y||
+        norms.append((np.linalg.norm(y), final[0], final[1]))
     return y
 
 

@@ -308,6 +308,76 @@ def test_error_within_paper_bound(oracle_mod):
         assert info["eval_bound"] < 1e-12
 
 
+
+# Hand-worked value of the evaluation-error bound of sec. II.B.3,
+#   sum_k u ||b_k|| + u ||c_k v - b_{k+2}|| + sqrt(d) gamma_d ||b_{k+1}||,
+# for n = 1 (d = n + 1 = 2 non-zeros per column of H), u = 2^-10 and the
+# three steps (1, 1, 0), (2, 3, 1), (0.5, 4, 2):
+#   gamma_2 = 2u / (1 - 2u) = (2/1024) / (1022/1024) = 1/511,
+#   u-terms = (1 + 1 + 2 + 3 + 0.5 + 4) / 1024 = 11.5 / 1024 = 23/2048,
+#   matvec terms = sqrt(2) * (1/511) * (0 + 1 + 2) = 3 sqrt(2) / 511,
+#   bound = 23/2048 + 3 sqrt(2)/511 = 0.019533...
+_BOUND_STEPS = [(1.0, 1.0, 0.0), (2.0, 3.0, 1.0), (0.5, 4.0, 2.0)]
+_BOUND_HAND = 23.0 / 2048.0 + 3.0 * np.sqrt(2.0) / 511.0
+
+
+def _bound_pin_holds(fn):
+    return abs(fn(_BOUND_STEPS, 1, 2.0 ** -10) - _BOUND_HAND) <= 1e-15
+
+
+def test_evaluation_bound_hand_value(oracle_mod):
+    """sec. II.B.3: the bound's value on a case worked by hand (above)."""
+    assert abs(_BOUND_HAND - 0.0195330918) < 1e-9
+    assert _bound_pin_holds(oracle_mod.evaluation_error_bound)
+
+
+def test_evaluation_bound_pin_catches_planted_mistakes():
+    """Plausible mistakes in the bound -- d = n instead of n + 1, a dropped
+    sqrt(d), u in place of gamma_d, a dropped u ||b_k|| term -- each miss the
+    hand-worked value."""
+    def d_is_n(norms, n, u):
+        g = n * u / (1.0 - n * u)
+        return sum(u * a + u * b + np.sqrt(n) * g * c for a, b, c in norms)
+
+    def no_sqrt(norms, n, u):
+        d = n + 1
+        g = d * u / (1.0 - d * u)
+        return sum(u * a + u * b + g * c for a, b, c in norms)
+
+    def u_for_gamma(norms, n, u):
+        d = n + 1
+        return sum(u * a + u * b + np.sqrt(d) * u * c for a, b, c in norms)
+
+    def no_bk(norms, n, u):
+        d = n + 1
+        g = d * u / (1.0 - d * u)
+        return sum(u * b + np.sqrt(d) * g * c for a, b, c in norms)
+
+    for broken in (d_is_n, no_sqrt, u_for_gamma, no_bk):
+        assert not _bound_pin_holds(broken), broken.__name__
+
+
+def test_evaluation_bound_norms_worked_by_hand(oracle_mod):
+    """The per-step norms the Clenshaw recurrence collects for the bound
+    (sec. II.B.3, Eq. recursion) on a 2 x 2 case worked by hand: d = (1/2, -1/2),
+    g = 1/4, v = (1, 0), c = (1, 1, 1).
+      b_2 = c_2 v = (1, 0);  b_1 = 2 H b_2 + c_1 v = 2 (1/2, 1/4) + (1, 0) = (2, 1/2);
+      y = H b_1 - b_2 + c_0 v = (1 + 1/8, 1/2 - 1/4) - (1, 0) + (1, 0) = (9/8, 1/4).
+    Steps k = 2, 1, 0: (||b_2||, ||c_2 v||, 0) = (1, 1, 0);
+    (||b_1||, ||c_1 v - b_3||, ||b_2||) = (sqrt(17)/2, 1, 1);
+    (||y||, ||c_0 v - b_2||, ||b_1||) = (sqrt(85)/8, 0, sqrt(17)/2)."""
+    d = np.array([0.5, -0.5])
+    v = np.array([1.0, 0.0], dtype=np.complex128)
+    c = np.array([1.0, 1.0, 1.0], dtype=np.complex128)
+    norms = []
+    y = oracle_mod.clenshaw(1, c, d, 0.25, v, norms)
+    assert np.allclose(y, [9.0 / 8.0, 0.25], atol=1e-15)
+    want = [(1.0, 1.0, 0.0), (np.sqrt(17.0) / 2, 1.0, 1.0), (np.sqrt(85.0) / 8, 0.0, np.sqrt(17.0) / 2)]
+    assert len(norms) == len(want)
+    for got, exp in zip(norms, want):
+        assert np.allclose(got, exp, atol=1e-15), (got, exp)
+
+
 # ---------------------------------------------------------------- CF
 
 def _err_curve(p, f, x):
