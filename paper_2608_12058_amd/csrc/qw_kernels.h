@@ -292,7 +292,7 @@ template <typename R> struct PassArgs {
 // Workgroups of a launch are dealt round-robin to the 8 XCDs (block b on XCD
 // b mod 8).  xcd_tile gives the blocks of each XCD a contiguous range of
 // tiles, so tiles that share DRAM pages (neighbouring rows) run on one XCD.
-__device__ __forceinline__ uint64_t xcd_tile(uint32_t b, uint32_t nb)
+__host__ __device__ __forceinline__ uint64_t xcd_tile(uint32_t b, uint32_t nb)
 {
     return (nb % 8 == 0) ? (uint64_t)(b % 8) * (nb / 8) + b / 8 : b;
 }
