@@ -18,8 +18,17 @@
  *     caller's workspace (size from qw_workspace_bytes / the batched and
  *     gradient size queries).
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Calls
- *     enqueue their kernels on it.  Entry points that need the spectral bound
- *     read 16 bytes back and synchronise the stream once.
+ *     enqueue their kernels on it.  Host synchronisation of an action call:
+ *       * the spectral bound (plain calls, qw_spectral_bound_*) is read back
+ *         once, 16 bytes; this one wait also covers the upload of (h, J);
+ *       * calls given (c, r) with the diagonal from (h, J) wait once for that
+ *         upload unless the norm monitor's read-back follows;
+ *       * the one-workgroup path (n <= 13, complex64 or complex128, no norm
+ *         monitor) waits once more, at its end, for its coefficient upload;
+ *       * the norm monitor reads back its K + 2 norms at the end (one wait);
+ *       * timing != 0 waits for the call's last event.
+ *     So a plain call of n >= 14 synchronises exactly once, at the read-back,
+ *     before its Clenshaw passes are enqueued; they run asynchronously.
  *   - Errors: every call returns a qw_status; nothing is thrown across the ABI.
  *     qw_last_error() returns a thread-local message for the last failure.
  *   - Calls on distinct workspaces may run concurrently from different threads.

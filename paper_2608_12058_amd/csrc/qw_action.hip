@@ -99,16 +99,32 @@ static WsLayout ws_layout(int n, int prec, bool otf)
 }
 
 
-// Upload h, J, build the Q table; returns the tables view.
+// Host copy of (h, J) for the upload of setup_tables.  The asynchronous copy
+// reads it when the stream reaches it, so it must outlive that point: calls
+// whose bound read-back follows the upload (which synchronises the stream)
+// need nothing more; otherwise the destructor synchronises once.
+struct HostTables {
+    hipStream_t s = nullptr;
+    std::vector<double> hj;
+    bool pending = false;
+    ~HostTables()
+    {
+        if (pending) (void)hipStreamSynchronize(s);
+    }
+};
+
+// Upload h, J (staged in `keep`), build the Q table; returns the tables view.
 static qw_status setup_tables(int n, const double *h, const double *J, char *ws, const WsLayout &L,
-                              hipStream_t s, EnergyTables *T)
+                              hipStream_t s, EnergyTables *T, HostTables &keep)
 {
     const int np = n * (n - 1) / 2;
-    std::vector<double> hj(n + np);
-    std::memcpy(hj.data(), h, n * sizeof(double));
-    if (np) std::memcpy(hj.data() + n, J, np * sizeof(double));
+    keep.s = s;
+    keep.hj.assign(n + np, 0.0);
+    std::memcpy(keep.hj.data(), h, n * sizeof(double));
+    if (np) std::memcpy(keep.hj.data() + n, J, np * sizeof(double));
     double *dhj = reinterpret_cast<double *>(ws + L.hj);
-    QW_HIP(hipMemcpyAsync(dhj, hj.data(), hj.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    QW_HIP(hipMemcpyAsync(dhj, keep.hj.data(), keep.hj.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    keep.pending = true;
     T->h = dhj;
     T->J = dhj + n;
     T->Q = reinterpret_cast<double *>(ws + L.q);
@@ -117,13 +133,13 @@ static qw_status setup_tables(int n, const double *h, const double *J, char *ws,
     const int nq = 1 << T->LB;
     hipLaunchKernelGGL(k_qtable<0>, dim3((nq + 255) / 256), dim3(256), 0, s, *T, const_cast<double *>(T->Q));
     QW_HIP(hipGetLastError());
-    QW_HIP(hipStreamSynchronize(s));  // hj lives on this stack frame
     return QW_OK;
 }
 
+// Min / max of the energies: the one synchronising read-back of a call.
 template <typename R>
 static qw_status minmax(int n, const R *diag, const EnergyTables *T, char *ws, const WsLayout &L,
-                        hipStream_t s, double *emin, double *emax)
+                        hipStream_t s, double *emin, double *emax, HostTables *keep = nullptr)
 {
     double *part = reinterpret_cast<double *>(ws + L.part);
     double *red = reinterpret_cast<double *>(ws + L.red);
@@ -143,6 +159,7 @@ static qw_status minmax(int n, const R *diag, const EnergyTables *T, char *ws, c
     double h2[2];
     QW_HIP(hipMemcpyAsync(h2, red, sizeof(h2), hipMemcpyDeviceToHost, s));
     QW_HIP(hipStreamSynchronize(s));
+    if (keep) keep->pending = false;   // the upload of (h, J) has been read
     *emin = h2[0];
     *emax = h2[1];
     return QW_OK;
@@ -181,12 +198,13 @@ static qw_status bound_impl(int n, const R *diag, const double *h, const double 
                             char *ws, const WsLayout &L, hipStream_t s, EnergyTables *T,
                             double *c, double *r)
 {
+    HostTables keep;
     if (!diag) {
-        qw_status st = setup_tables(n, h, J, ws, L, s, T);
+        qw_status st = setup_tables(n, h, J, ws, L, s, T, keep);
         if (st != QW_OK) return st;
     }
     double emin, emax;
-    qw_status st = minmax<R>(n, diag, T, ws, L, s, &emin, &emax);
+    qw_status st = minmax<R>(n, diag, T, ws, L, s, &emin, &emax, &keep);
     if (st != QW_OK) return st;
     if (!finite(emin) || !finite(emax)) { set_error("diagonal has non-finite entries"); return QW_EINVAL; }
     *c = 0.5 * (emax + emin);
@@ -399,6 +417,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     timer.mark(0);
 
     EnergyTables T{};
+    HostTables keep;   // (h, J) staged for an upload with no read-back after it
     double c = 0.0, r = 0.0;
     if (poly && info && info->monitor) { set_error("the norm monitor applies to exp(-itH) only"); return QW_EINVAL; }
     const bool monitor = !poly && ((info && info->monitor) || (given_cr && !prep));
@@ -410,7 +429,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
             if (prep) {
                 T = prep->T;
             } else {
-                st = setup_tables(n, h, J, ws, L, s, &T);
+                st = setup_tables(n, h, J, ws, L, s, &T, keep);
                 if (st != QW_OK) return st;
             }
         }
@@ -538,6 +557,7 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
                            (const OnchipItem<R> *)ditem, (const int *)nullptr, 1);
         QW_HIP(hipGetLastError());
         QW_HIP(hipStreamSynchronize(s));  // host copies of ch/item go out of scope
+        keep.pending = false;
         return timer.finish(info);
     }
 
@@ -671,8 +691,10 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     if (tst != QW_OK) return tst;
     tst = ptimer.finish(info);
     if (tst != QW_OK || !monitor) return tst;
-    return check_growth(n, K, alpha, tol, sizeof(R) == 4 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53), norms, s,
-                        info);
+    tst = check_growth(n, K, alpha, tol, sizeof(R) == 4 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53), norms, s,
+                       info);
+    keep.pending = false;   // check_growth synchronised the stream
+    return tst;
 }
 
 template <typename R>
@@ -750,9 +772,10 @@ qw_status prepare_energy(int n, const double *h, const double *J, void *workspac
     }
     char *ws = static_cast<char *>(workspace);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    qw_status st = setup_tables(n, h, J, ws, L, s, T);
+    HostTables keep;
+    qw_status st = setup_tables(n, h, J, ws, L, s, T, keep);
     if (st != QW_OK) return st;
-    return minmax<R>(n, nullptr, T, ws, L, s, emin, emax);
+    return minmax<R>(n, nullptr, T, ws, L, s, emin, emax, &keep);
 }
 
 template <typename R>
