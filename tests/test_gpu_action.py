@@ -6,12 +6,18 @@ shape of the multi-pass path: 2^12-amplitude tiles with 1024 threads (n <= 20 in
 complex64, <= 21 in complex128), 2^13 tiles with 1024 threads (n = 21) and 512
 threads (n = 22), 2^14 tiles (n = 23, 24), the split shape of three orientations
 (n = 25..28: 2^12 tiles on the contiguous one); at the full 28-qubit
-workload, properties that hold at any size and closed forms evaluated one
-sampled amplitude at a time.
+workload, properties that hold at any size, closed forms evaluated one
+sampled amplitude at a time, and 4096 sampled amplitudes of the oracle's result
+for the benchmark workload itself (tests/golden/action_n28_bench.json).  The
+split shape is compared with the oracle over the whole vector at 25-27 qubits,
+with negative gamma and negative t among the cases.
 
 Tolerances: complex128 <= 1e-12 against the oracle run at the same truncation
 tolerance (identical degree K), complex64 <= 1e-5 against the oracle at 1e-13.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -77,6 +83,11 @@ CASES = [
     (22, 0.7, 0.4, 9),
     (23, 1.0, 0.3, 10),
     (24, 0.8, 0.2, 12),
+    # negative gamma (complex64 rounds gamma/r towards zero by magnitude) and
+    # negative t, on the one-workgroup, narrow and default shapes
+    (11, -0.9, 1.2, 13),
+    (19, 0.7, -0.9, 14),
+    (22, -1.1, -0.3, 15),
 ]
 
 
@@ -280,4 +291,86 @@ def test_n28_sampled_closed_forms(env, oracle_mod, prec):
     ref = oracle_mod.closed_form_gamma0_amps(N28, h, J, 5.0, amp, idx[:512])
     assert rel(got, ref) <= (C64_TOL if prec == 64 else C128_TOL)
     del y, psi
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------ split shape (25-28 qubits) vs the oracle
+
+SPLIT_CASES = [
+    # n, gamma, t, seed: K = 85, 70, 69, 75 at tol 1e-13
+    (25, 0.9, 1.0, 525),
+    (26, -0.7, 0.8, 526),
+    (27, 1.1, -0.6, 527),
+    (25, -1.2, -0.7, 535),
+]
+
+
+@pytest.mark.parametrize("n,gamma,t,seed", SPLIT_CASES)
+def test_split_shape_vs_oracle(env, oracle_mod, n, gamma, t, seed):
+    """The kernels of the benchmark's launch configuration (complex64: contiguous
+    orientation on 2^12 tiles with 1024 threads, strided add passes on 2^13 tiles
+    with 1024 threads, strided fused passes with 512; from 26 qubits the top
+    orientation's fused pass rebuilds the diagonal from h and J) on a generic SK
+    instance and a random state, compared over the whole vector with the oracle
+    at tol 1e-13: complex64 from (h, J) and from a stored diagonal <= 1e-5;
+    complex128 at the same tolerance (same degree) <= 1e-12."""
+    torch, qw = env
+    h, J = synth.sk_instance(n, seed)
+    E = oracle_mod.energies(n, h, J)
+    psi = synth.random_state(n, seed + 1000)
+    oinfo = {}
+    ref = oracle_mod.expm_action(n, E, gamma, t, psi, 1e-13, info=oinfo)
+    assert oinfo["K"] >= 50
+    y, info = _run(env, n, psi, gamma, t, 2.0 ** -23, 64, h=h, J=J)
+    assert info["passes"] == 3
+    e64 = rel(y, ref)
+    y, _ = _run(env, n, psi, gamma, t, 2.0 ** -23, 64, diag_np=E)
+    e64d = rel(y, ref)
+    y, info128 = _run(env, n, psi, gamma, t, 1e-13, 128, h=h, J=J)
+    e128 = rel(y, ref)
+    print(f"n={n} gamma={gamma} t={t}: K {oinfo['K']} / c64 K {info['K']}: c64 (h, J) {e64:.2e}, "
+          f"c64 diag {e64d:.2e}, c128 {e128:.2e}", flush=True)
+    assert info128["K"] == oinfo["K"]
+    assert e64 <= C64_TOL and e64d <= C64_TOL
+    assert e128 <= C128_TOL
+    del y
+    torch.cuda.empty_cache()
+
+
+GOLDEN28 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "action_n28_bench.json")
+
+
+@pytest.mark.parametrize("prec", [64, 128])
+def test_n28_bench_workload_vs_oracle_golden(env, prec):
+    """The benchmark workload (SK seed 0, gamma = 1, t = 5, |+>, 28 qubits) in
+    the benchmark's launch configuration (caller output and workspace) against
+    4096 amplitudes and the norm of the oracle's result, written by
+    tests/golden/make_bench_golden.py: complex64 at 2^-23 against the oracle at
+    1e-13 (<= 1e-5 over the samples); complex128 at 1e-12 against the oracle at
+    1e-12, same degree (<= 1e-12)."""
+    torch, qw = env
+    with open(GOLDEN28) as f:
+        gold = json.load(f)
+    n = gold["n"]
+    assert (n, gold["gamma"], gold["t"], gold["seed"]) == (N28, 1.0, 5.0, 0)
+    h, J = synth.sk_instance(n, 0)
+    cdt = torch.complex64 if prec == 64 else torch.complex128
+    tol = 2.0 ** -23 if prec == 64 else 1e-12
+    run = gold["runs"]["1e-13" if prec == 64 else "1e-12"]
+    psi = synth.plus_state_torch(n, "cuda", cdt)
+    out = torch.empty_like(psi)
+    ws = qw.Workspace.for_problem(n, prec)
+    y, info = qw.expm_action(psi, 1.0, 5.0, h=h, J=J, tol=tol, out=out, workspace=ws)
+    if prec == 128:
+        assert info["K"] == run["K"]
+    idx = torch.as_tensor(np.asarray(gold["idx"], dtype=np.int64), device="cuda")
+    got = y[idx].cpu().numpy().astype(np.complex128)
+    ref = np.asarray(run["re"]) + 1j * np.asarray(run["im"])
+    err = rel(got, ref)
+    nrm = torch.linalg.vector_norm(y.to(torch.complex128)).item()
+    print(f"n28 bench workload c{prec}: K {info['K']} (oracle {run['K']}), sampled rel err {err:.2e}, "
+          f"norm {nrm:.12f} (oracle {run['norm']:.12f})", flush=True)
+    assert err <= (C64_TOL if prec == 64 else C128_TOL)
+    assert abs(nrm - run["norm"]) <= (C64_TOL if prec == 64 else C128_TOL)
+    del y, out, ws, psi
     torch.cuda.empty_cache()

@@ -32,6 +32,9 @@ def mixed_instances():
         (3, 0.7, 2.0, 1e-6, 1), (8, 1.3, 5.0, 1e-6, 2), (12, 0.4, 11.0, 1e-6, 3), (13, 1.9, 0.3, 1e-6, 4),
         (14, 0.9, 3.0, 1e-6, 5), (15, 1.1, 0.0, 1e-6, 6), (16, 0.2, 19.0, 1e-6, 7), (18, 1.6, 1.5, 2.0 ** -23, 8),
         (17, 0.0, 2.0, 1e-6, 9), (20, 0.5, 0.7, 1e-6, 10), (13, 1.0, 4.0, 1e-6, 11), (21, 1.0, 0.4, 1e-6, 12),
+        # the widest high-bit group (22 qubits: 9 bits, 128-byte rows), 19 qubits,
+        # negative gamma and negative t
+        (22, 0.8, 0.5, 1e-6, 13), (19, 1.2, 0.9, 1e-6, 14), (16, -0.9, 1.5, 1e-6, 15), (18, 0.6, -1.1, 1e-6, 16),
     ]
     out = []
     for n, g, t, tol, seed in spec:
@@ -141,8 +144,9 @@ def test_tune_cache_roundtrip(env, tmp_path):
 
 def test_config3_batched_256(env, oracle_mod):
     """256 SK instances, n ~ U{12..22}, t ~ U(0.1, 20), gamma ~ U(0.2, 2),
-    complex64, tol 1e-6: norms conserved, every small instance and a sample of
-    large ones against the oracle, a sample against the single-instance path."""
+    complex64, tol 1e-6: norms conserved, small instances, a sample of 14-16
+    qubit ones and the two 22-qubit ones of shortest time against the oracle, a
+    sample against the single-instance path."""
     torch, qw = env
     insts = synth.batch_instances(256, 0)
     for ins in insts:
@@ -160,7 +164,9 @@ def test_config3_batched_256(env, oracle_mod):
     rng = np.random.default_rng(3)
     small = [i for i, ins in enumerate(insts) if ins["n"] <= 13]
     large = [i for i, ins in enumerate(insts) if 14 <= ins["n"] <= 16]
-    check = small[:8] + list(rng.choice(large, 4, replace=False))
+    # 22-qubit instances (9-bit high group), the two with the shortest times
+    top = sorted((i for i, ins in enumerate(insts) if ins["n"] == 22), key=lambda i: insts[i]["t"])[:2]
+    check = small[:8] + list(rng.choice(large, 4, replace=False)) + top
     for i in check:
         ins = insts[i]
         n = ins["n"]
