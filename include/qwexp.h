@@ -234,6 +234,21 @@ qw_status qw_expm_action_c128(int n, const double *diag, const double *h, const 
                               double tol, qw_method method,
                               void *workspace, size_t ws_bytes, void *stream, qw_info *info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * action as qw_expm_action_c64, same kernels and results, with no workspace
+ * argument.  Its scratch is a fixed 22 MiB device array inside the library,
+ * one per GPU, held until the process ends, enough for n <= 20 qubits; larger n
+ * returns QW_EINVAL with a message.  The array's device address is looked up
+ * once per device (the device current at the call).  Every call on one GPU
+ * shares that GPU's array and nothing in it needs clearing between calls, but
+ * calls that overlap on one GPU (on different streams or threads) race on it
+ * and must be serialised by the caller.  The call allocates nothing on the
+ * device; host synchronisation as qw_expm_action_c64. */
+qw_status qw_expm_action_c64_noalloc(int n, const float *diag, const double *h, const double *J,
+                                     double gamma, double t, const void *psi_in, void *psi_out,
+                                     double tol, qw_method method, void *stream, qw_info *info);
+
 /* ---- batched form (section III.A: many instances per launch) ----------- */
 
 /* One instance of a batch.  Couplings h (n doubles) then J (n(n-1)/2 doubles,

@@ -65,6 +65,8 @@ def _declare(lib):
     for name in ("qw_expm_action_c64", "qw_expm_action_c128"):
         f = getattr(lib, name)
         f.argtypes = [_i, _vp, _dp, _dp, _d, _d, _vp, _vp, _d, _i, _vp, _sz, _vp, ctypes.POINTER(QwInfo)]
+    lib.qw_expm_action_c64_noalloc.argtypes = [_i, _vp, _dp, _dp, _d, _d, _vp, _vp, _d, _i, _vp,
+                                               ctypes.POINTER(QwInfo)]
     for name in ("qw_expm_action_c64_bounded", "qw_expm_action_c128_bounded"):
         f = getattr(lib, name)
         f.argtypes = [_i, _vp, _dp, _dp, _d, _d, _d, _d, _vp, _vp, _d, _i, _vp, _sz, _vp, ctypes.POINTER(QwInfo)]
@@ -247,6 +249,37 @@ def expm_action(psi, gamma: float, t: float, *, diag=None, h=None, J=None, tol: 
                   _vp(psi.data_ptr()), _vp(out.data_ptr()), float(tol), _METHODS[method], _vp(workspace.ptr()),
                   workspace.nbytes, _stream_ptr(stream), ctypes.byref(info)))
     return out, info.as_dict()
+
+
+def expm_action_noalloc(psi, gamma: float, t: float, out, *, diag=None, h=None, J=None,
+                        tol: float = 2.0 ** -23, method: str = "cheb", stream=None, timing: int = 0):
+    """exp(-i t H) psi in complex64 through qw_expm_action_c64_noalloc: no
+    workspace (the library's fixed device scratch, n <= 20) and a caller-given
+    out, so nothing is allocated on the device.  Returns the info dict."""
+    torch = _torch()
+    if not (psi.is_cuda and psi.is_contiguous() and psi.dim() == 1 and psi.dtype == torch.complex64):
+        raise ValueError("psi must be a contiguous 1-D complex64 CUDA tensor")
+    N = psi.numel()
+    n = N.bit_length() - 1
+    if N != (1 << n):
+        raise ValueError("len(psi) must be a power of two")
+    if out.dtype != psi.dtype or out.numel() != N or not out.is_contiguous():
+        raise ValueError("out must match psi")
+    if diag is not None:
+        if diag.dtype != torch.float32 or not diag.is_contiguous() or diag.numel() != N or not diag.is_cuda:
+            raise ValueError("diag must be a contiguous float32 CUDA vector of 2^n energies")
+        hp = Jp = None
+    else:
+        if h is None or J is None:
+            raise ValueError("give diag, or h and J")
+        _h, hp = _host_f64(h, n)
+        _J, Jp = _host_f64(J, n * (n - 1) // 2)
+    info = QwInfo()
+    info.timing = int(timing)
+    _check(lib().qw_expm_action_c64_noalloc(int(n), _vp(diag.data_ptr()) if diag is not None else None, hp, Jp,
+                                            float(gamma), float(t), _vp(psi.data_ptr()), _vp(out.data_ptr()),
+                                            float(tol), _METHODS[method], _stream_ptr(stream), ctypes.byref(info)))
+    return info.as_dict()
 
 
 QW_BASIS_CHEB, QW_BASIS_MONO = 0, 1

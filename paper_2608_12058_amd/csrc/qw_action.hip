@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -52,6 +53,14 @@ __global__ void __launch_bounds__(256) k_minmax_diag(const R *d, uint64_t N, dou
         mx = fmax(mx, v);
     }
     block_minmax(mn, mx, part);
+}
+
+template <int D = 0>
+__global__ void __launch_bounds__(256) k_fill_zero(double *x, uint64_t count)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        x[i] = 0.0;
 }
 
 template <typename R>
@@ -576,7 +585,9 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     double *norms = reinterpret_cast<double *>(ws + L.norms);
     if (monitor) {
         if (K + 2 > KMAX_MON) { set_error("degree too large for the norm monitor"); return QW_ENOMEM; }
-        QW_HIP(hipMemsetAsync(norms, 0, (K + 2) * sizeof(double), s));
+        // cleared by a kernel, not a memset node, so that the call can be captured
+        hipLaunchKernelGGL(k_fill_zero<0>, dim3(grid_for(K + 2, 256, 256)), dim3(256), 0, s, norms,
+                           (uint64_t)(K + 2));
         hipLaunchKernelGGL(k_norm2<R>, dim3(grid_for(nvec, 256 * 8, 4096)), dim3(256), 0, s,
                            reinterpret_cast<const V *>(psi), nvec, norms + K + 1);
     }
@@ -809,11 +820,64 @@ template qw_status scaled_action<double>(int, const double *, const double *, co
                                          double, double, double, const void *, void *, double, void *, size_t, void *,
                                          qw_info *);
 
+// ---------------------------------------------------------------------------
+// Entry point without a caller workspace: its scratch is a file-scope device
+// array of fixed size (each GPU the library runs on holds one until the
+// process ends), sized for the complex64 workspace of NOALLOC_NMAX qubits.
+// Host code must not pass the array's name to a kernel (it is a host-side
+// stand-in there): its device address is taken once per device with
+// hipGetSymbolAddress and used instead.
+// ---------------------------------------------------------------------------
+static constexpr int NOALLOC_NMAX = 20;
+static constexpr size_t NOALLOC_BYTES = size_t(22) << 20;   // >= ws_layout(20, 64, false).total
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+static constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's scratch array, looked up on first use with
+// the device current.
+static qw_status scratch_for_current_device(void **ptr)
+{
+    int dev = -1;
+    QW_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) { set_error("device index out of range"); return QW_EINVAL; }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        QW_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255) != 0) { set_error("scratch symbol address"); return QW_EHIP; }
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return QW_OK;
+}
+
 }  // namespace qw
 
 using namespace qw;
 
 extern "C" {
+
+qw_status qw_expm_action_c64_noalloc(int n, const float *diag, const double *h, const double *J, double gamma,
+                                     double t, const void *psi_in, void *psi_out, double tol, qw_method method,
+                                     void *stream, qw_info *info)
+{
+    if (n < 1 || n > NOALLOC_NMAX) {
+        set_error("qw_expm_action_c64_noalloc: n must be in 1.." + std::to_string(NOALLOC_NMAX) +
+                  " (its fixed device scratch holds the workspace of " + std::to_string(NOALLOC_NMAX) + " qubits)");
+        return QW_EINVAL;
+    }
+    const size_t need = ws_layout(n, 64, false).total;
+    if (need > NOALLOC_BYTES) { set_error("internal: scratch array too small"); return QW_ENOMEM; }
+    void *ws = nullptr;
+    const qw_status st = scratch_for_current_device(&ws);
+    if (st != QW_OK) return st;
+    return action_impl<float>(n, diag, h, J, gamma, t, psi_in, psi_out, tol, (int)method, ws, NOALLOC_BYTES,
+                              stream, info);
+}
+
 
 const char *qw_last_error(void) { return g_err.c_str(); }
 const char *qw_version(void) { return "qwexp 0.10 (gfx950, fused passes, split tiles, fused start, top-orientation diagonal on the fly)"; }
