@@ -29,7 +29,11 @@ if HERE not in sys.path:
 METRIC = "n=28 exp(-itH)ψ: amps·terms/s, HBM GB/s % peak; fp32/batched/grad vs fp64 plain"
 UNIT = "amps·terms/s"
 PEAK_HBM_GBPS = 8000.0
-BYTES_PER_AMP_TERM = {64: 36, 128: 72}     # algorithmic bytes per amplitude and term
+# algorithmic bytes per amplitude and term: read b_{k+1}, b_{k+2}, psi and
+# write b_k (8 B each in complex64), plus 4 B of stored diagonal when the
+# passes read one; 72 B in complex128 with its double diagonal
+BYTES_PER_AMP_TERM = {64: 36, 128: 72}
+BYTES_PER_AMP_TERM_OTF = 32
 BYTES_INIT = {64: 0, 128: 0}               # b_K = c_K psi is read by the first term's passes
 
 
@@ -392,18 +396,23 @@ def main():
     pass_ms = pinfo["pass_ms"][:P]
     terms = K  # K-1 recurrence terms + the final step, each P passes
     term_ms = loop_ms / terms
-    alg_bytes_term = BYTES_PER_AMP_TERM[64] * N
+    # the passes that would read a stored diagonal (START / FUSED, on the end
+    # orientations) all rebuild it: the algorithmic figure is then 32 B
+    ends = {0, P - 1}
+    otf_all = all((pinfo["otf_mask"] >> p) & 1 for p in ends)
+    alg_per_amp = BYTES_PER_AMP_TERM_OTF if otf_all else BYTES_PER_AMP_TERM[64]
+    alg_bytes_term = alg_per_amp * N
     achieved = (BYTES_INIT[64] * N + alg_bytes_term * terms) / (loop_ms * 1e-3) / 1e9
+    achieved_36 = 36 * N * terms / (loop_ms * 1e-3) / 1e9
     # bytes each orientation moves per term under the fused schedule: the two
-    # end orientations alternate a fused pass (44 B/amp; 40 on the fly) every
-    # other term, the middle ones add (24 B/amp) every term
-    fused_b = 44 * N
-    # from 26 to 28 qubits (complex64, diagonal from h and J) the fused pass of the
-    # top orientation rebuilds the diagonal instead of reading it: 40 B/amp
-    fused_top = 40 * N if 26 <= n <= 28 else fused_b
-    per_term = ([fused_b / 2 if p == 0 else fused_top / 2 if p == P - 1 else 24 * N for p in range(P)]
-                if P > 1 else [36 * N])
-    passes = [{"orientation": p, "avg_us_per_term": pass_ms[p] / terms * 1e3, "moved_bytes_per_term": per_term[p],
+    # end orientations alternate a fused pass every other term (44 B/amp, 40
+    # where the pass rebuilds the diagonal: bit o of otf_mask), the middle ones
+    # add (24 B/amp) every term
+    mask = pinfo.get("otf_mask", 0)
+    fused = [(40 if (mask >> p) & 1 else 44) * N for p in range(P)]
+    per_term = ([fused[p] / 2 if p in (0, P - 1) else 24 * N for p in range(P)] if P > 1 else [36 * N])
+    passes = [{"orientation": p, "rebuilds_diagonal": bool((mask >> p) & 1),
+               "avg_us_per_term": pass_ms[p] / terms * 1e3, "moved_bytes_per_term": per_term[p],
                "moved_GBps": per_term[p] / (pass_ms[p] / terms * 1e-3) / 1e9} for p in range(P)]
 
     traffic = None
@@ -421,12 +430,15 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
         "config": {"workload": f"SK spin glass n={n} (seed 0, J~N(0,1/n), h~N(0,1)), gamma=1, t=5, "
-                               f"tol=2^-23, psi0=|+>, complex64 state, fp32 diagonal generated on GPU (stored; rebuilt per tile in the top-orientation pass)",
+                               f"tol=2^-23, psi0=|+>, complex64 state, fp32 diagonal rebuilt per tile from (h, J) in the fused passes",
                    "n": n, "K": K, "passes_per_term": P, "radius_r": infos[0]["radius_r"],
                    "a": infos[0]["a"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBPS, "traffic": traffic,
-                     "kernel": "Clenshaw term (all passes), 36 B/amp algorithmic",
+                     "kernel": f"Clenshaw term (all passes), {alg_per_amp} B/amp algorithmic",
+                     "alg_bytes_per_amp_term": alg_per_amp,
+                     # the same time priced at the 36 B/amp of a stored float diagonal
+                     "frac_at_36B": achieved_36 / PEAK_HBM_GBPS,
                      "avg_term_us": term_ms * 1e3,
                      # HBM rate of the bytes the counters saw per term (traffic), same term time
                      "traffic_GBps": (traffic / (term_ms * 1e-3) / 1e9) if traffic else None,

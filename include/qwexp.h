@@ -77,6 +77,8 @@ typedef struct {
     double growth;      /* out (monitor): max over k of ||b_k|| / its limit for a
                            valid bound (> 1 means QW_EDIVERGE)                     */
     double out_norm;    /* out (monitor): ||psi_out||                             */
+    int otf_mask;       /* out: bit o set if the passes of orientation o rebuild
+                           the diagonal from (h, J) instead of reading it         */
 } qw_info;
 
 /* ------------------------------------------------------------------------

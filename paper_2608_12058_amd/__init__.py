@@ -36,7 +36,7 @@ class QwInfo(ctypes.Structure):
                 ("trunc_bound", ctypes.c_double), ("eval_bound", ctypes.c_double),
                 ("timing", ctypes.c_int), ("setup_ms", ctypes.c_float), ("loop_ms", ctypes.c_float),
                 ("pass_ms", ctypes.c_float * 4), ("monitor", ctypes.c_int), ("growth", ctypes.c_double),
-                ("out_norm", ctypes.c_double)]
+                ("out_norm", ctypes.c_double), ("otf_mask", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}

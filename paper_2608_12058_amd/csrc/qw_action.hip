@@ -497,12 +497,15 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     const double norm_c = (es != 0.0) ? c / es : 0.0, norm_inv_r = es * inv_r;
     R *dn = otf ? nullptr : reinterpret_cast<R *>(ws + L.d);
     double *qt = reinterpret_cast<double *>(ws + L.qt);
-    // the top orientation of the split shape rebuilds the diagonal when it can
-    const bool otf_top = !otf && diag == nullptr && sizeof(R) == 4 && tile_cfg_for<R>(n).tb0 > 0 && n >= OTF_TOP_NMIN;
-    auto orient_otf = [&](const PassPlan &pl) { return otf || (otf_top && pl.L > 0 && pl.g0 + pl.h == n); };
-    double *ft = (otf || otf_top) ? reinterpret_cast<double *>(ws + L.ft) : nullptr;
+    // orientations and launch shapes; the end orientations rebuild the diagonal
+    // where the plan says so, and the stored one is formed only if a pass reads it
+    const std::vector<OrientSpec> plan = action_plan<R>(n, diag == nullptr);
+    bool any_otf = false;
+    for (const OrientSpec &o : plan) any_otf = any_otf || o.otf;
+    if (any_otf && !(L.ft != size_t(-1))) { set_error("internal: no per-tile field table for this size"); return QW_EINVAL; }
+    double *ft = any_otf ? reinterpret_cast<double *>(ws + L.ft) : nullptr;
     const uint64_t ft_stride = (N >> TB_NARROW) * TILE_FIELDS;   // doubles per orientation
-    if (!otf) {
+    if (!otf && plan_reads_diag(plan)) {
         if (diag) {
             hipLaunchKernelGGL(k_normalize_diag<R>, dim3(grid_for(N, 256 * 8, 1 << 16)), dim3(256), 0, s,
                                diag, N, c, inv_r, dn);
@@ -534,14 +537,13 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         }
     }
     const bool horner = poly && poly->horner;
-    const TileCfg cfg = tile_cfg_for<R>(n);
-    const int tb = cfg.tb;
-    const std::vector<PassPlan> plan = plan_passes(n, tb, Cfg<R>::LMIN, cfg.tb0);
     if (info) {
         info->K = K;
         info->a = a;
         info->trunc_bound = err;
         info->passes = (int)plan.size();
+        for (size_t o = 0; o < plan.size(); ++o)
+            if (plan[o].otf) info->otf_mask |= 1 << o;
     }
 
     if (n <= Cfg<R>::TB && !monitor) {
@@ -592,25 +594,25 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
                            reinterpret_cast<const V *>(psi), nvec, norms + K + 1);
     }
     const int P = (int)plan.size();
-    if (otf || otf_top) {
-        for (int o = 0; o < P; ++o) {
-            if (!orient_otf(plan[o])) continue;
-            // the on-the-fly shapes (default 2^13 tiles with 512 threads, wide 2^14
-            // with 1024) fill every tile: the split pair table needs L + h = TB
-            const TileCfg pc = pass_cfg<R>(cfg, plan[o], PM_FUSED);
-            const int log_nt = (pc.nt == 1024) ? 10 : 9;
-            if (plan[o].L + plan[o].h != pc.tb || (pc.nt != 1024 && pc.nt != 512) || pc.tb - log_nt > QS_MAX_R) {
-                set_error("internal: on-the-fly tile shape");
-                return QW_EINVAL;
-            }
-            hipLaunchKernelGGL(k_qsplit_orient<0>, dim3(((1 << log_nt) + 255) / 256), dim3(256), 0, s, T.h, n,
-                               plan[o].L, plan[o].g0, plan[o].h, log_nt, norm_inv_r,
-                               qt + (size_t)o * (1 << TB_WIDE));
-            const uint64_t nt = N >> (plan[o].L + plan[o].h);
-            hipLaunchKernelGGL(k_tile_fields<0>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, T.h, n,
-                               plan[o].L, plan[o].g0, plan[o].h, nt, norm_c, norm_inv_r,
-                               ft + (size_t)o * ft_stride);
+    if (P > 4) { set_error("internal: more than four orientations"); return QW_EINVAL; }
+    for (int o = 0; o < P; ++o) {
+        if (!plan[o].otf) continue;
+        // the on-the-fly shapes (2^13 tiles with 512 threads, 2^14 with 1024)
+        // fill every tile: the split pair table needs L + h = TB
+        const PassPlan &pl = plan[o].pl;
+        const TileCfg &pc = plan[o].fused;
+        const int log_nt = (pc.nt == 1024) ? 10 : 9;
+        const bool shape_ok = sizeof(R) == 4 && ((pc.tb == TB_WIDE && pc.nt == NT_WIDE) ||
+                                                 (pc.tb == Cfg<R>::TB && pc.nt == Cfg<R>::NT));
+        if (pl.L + pl.h != pc.tb || !shape_ok || pc.tb - log_nt > QS_MAX_R) {
+            set_error("internal: on-the-fly tile shape");
+            return QW_EINVAL;
         }
+        hipLaunchKernelGGL(k_qsplit_orient<0>, dim3(((1 << log_nt) + 255) / 256), dim3(256), 0, s, T.h, n, pl.L,
+                           pl.g0, pl.h, log_nt, norm_inv_r, qt + (size_t)o * (1 << TB_WIDE));
+        const uint64_t nt = N >> (pl.L + pl.h);
+        hipLaunchKernelGGL(k_tile_fields<0>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, T.h, n, pl.L,
+                           pl.g0, pl.h, nt, norm_c, norm_inv_r, ft + (size_t)o * ft_stride);
     }
     timer.mark(1);
     // Clenshaw start b_K = c_K psi (b_{K+1} = 0 is never read: the first pass
@@ -635,7 +637,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
     auto scale_of = [horner](int k) { return (k == 0 || horner) ? R(1) : R(2); };
     pa.sub = horner ? R(0) : R(1);
     for (const SchedPass &sp : sched) {
-        const PassPlan &pl = plan[sp.orient];
+        const OrientSpec &os = plan[sp.orient];
+        const PassPlan &pl = os.pl;
         double cr = 0.0, ci = 0.0;
         pa.b1 = X;
         pa.b1_scaled = 0;
@@ -650,8 +653,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         pa.g0 = pl.g0;
         pa.h = pl.h;
         pa.Qt = qt + (size_t)sp.orient * (1 << TB_WIDE);
-        const bool pass_otf = orient_otf(pl);
-        pa.Ft = pass_otf ? ft + (size_t)sp.orient * ft_stride : nullptr;
+        const bool pass_otf = os.otf && sp.mode != PM_ADD;
+        pa.Ft = os.otf ? ft + (size_t)sp.orient * ft_stride : nullptr;
         pa.pr = R(1);
         pa.pi = R(0);
         pa.dst2 = nullptr;
@@ -686,14 +689,8 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         pa.cr = (R)cr;
         pa.ci = (R)ci;
         const uint64_t ntiles = N >> (pl.L + pl.h);
-        // XCD-major tile order for the default, split and wide complex64 tiles,
-        // except on the orientation of the top bits (measured per term at 28
-        // qubits: 3415 us in launch order, 3393 XCD-major everywhere, 3374
-        // everywhere but the top orientation; wide tiles at 32 qubits: 2127 ->
-        // 2090 ms for 38 terms; no gain in complex128)
-        const bool xcd_shape = (cfg.tb == Cfg<R>::TB && cfg.nt == Cfg<R>::NT) || cfg.tb == TB_WIDE;
-        pa.xcd_order = (sizeof(R) == 4 && xcd_shape && pl.g0 + pl.h < n) ? 1 : 0;
-        launch_pass<R>(pa, sp.mode, pass_otf, ntiles, s, pass_cfg<R>(cfg, pl, sp.mode));
+        pa.xcd_order = os.xcd;
+        launch_pass<R>(pa, sp.mode, pass_otf, ntiles, s, sp.mode == PM_ADD ? os.add : os.fused);
         ptimer.mark(sp.orient);
         if (sp.mode == PM_FUSED || (sp.mode == PM_START && P == 1)) std::swap(X, Y);
     }
@@ -726,13 +723,13 @@ static qw_status bound_entry(int n, const R *diag, const double *h, const double
 // flipped partner must stay inside the tile.
 int check_plan(int n, int prec)
 {
-    const int TB = (prec == 64) ? tile_cfg_for<float>(n).tb : tile_cfg_for<double>(n).tb;
-    const int TB0 = (prec == 64) ? tile_cfg_for<float>(n).tb0 : tile_cfg_for<double>(n).tb0;
-    std::vector<PassPlan> plan = plan_passes(n, TB, (prec == 64) ? Cfg<float>::LMIN : Cfg<double>::LMIN, TB0);
+    const std::vector<OrientSpec> spec = (prec == 64) ? action_plan<float>(n, true) : action_plan<double>(n, true);
     const uint64_t N = uint64_t(1) << n;
     int covered_bits = 0;
-    for (const PassPlan &p : plan) {
-        if (p.L + p.h > TB || p.L + p.h > n) return -1;
+    for (const OrientSpec &os : spec) {
+        const PassPlan &p = os.pl;
+        if (p.L + p.h > os.fused.tb || p.L + p.h > os.add.tb || p.L + p.h > n) return -1;
+        if (os.otf && p.L + p.h != os.fused.tb) return -7;
         if (p.L > p.g0 && p.g0 != 0) return -2;
         std::vector<uint8_t> seen(N, 0);
         const uint64_t ntiles = N >> (p.L + p.h);
@@ -752,7 +749,7 @@ int check_plan(int n, int prec)
         }
         covered_bits += p.h;
     }
-    return covered_bits == n ? (int)plan.size() : -6;
+    return covered_bits == n ? (int)spec.size() : -6;
 }
 
 template <typename R>
@@ -880,7 +877,7 @@ qw_status qw_expm_action_c64_noalloc(int n, const float *diag, const double *h, 
 
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.10 (gfx950, fused passes, split tiles, fused start, top-orientation diagonal on the fly)"; }
+const char *qw_version(void) { return "qwexp 0.11 (gfx950, fused passes, per-orientation launch plans, contiguous middle orientation, diagonal rebuilt in the end orientations)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {

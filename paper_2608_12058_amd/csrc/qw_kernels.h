@@ -883,6 +883,79 @@ template <typename R> inline TileCfg pass_cfg(const TileCfg &cfg, const PassPlan
     return p;
 }
 
+// One orientation of an action call's pass plan with its launch shapes.  The
+// fused schedule (fused_schedule) runs START / FUSED passes only on the end
+// orientations (the first and last of the plan) and an ADD pass on every
+// middle one in every term, so where a bit group goes in the plan decides how
+// often its kernel runs.
+struct OrientSpec {
+    PassPlan pl;     // L, g0, h
+    TileCfg fused;   // shape of its START / FUSED passes
+    TileCfg add;     // shape of its ADD passes
+    bool otf;        // START / FUSED rebuild the diagonal from the tile fields
+    int xcd;         // blocks take tiles in XCD-major order (xcd_tile)
+};
+
+// Complex64 at 25-28 and 32 qubits: the contiguous orientation in the middle
+// (an add pass every term, 12 or 13 bits), the two high groups at the ends
+// (one fused pass each every other term).  The fused pass of the lower high
+// group runs on 2^14-amplitude tiles with rows of >= 512 B, the top group's on
+// 2^13 (25-28 qubits) or 2^14 (32 qubits) tiles.  Both ends rebuild the
+// diagonal when it comes from (h, J) (from 26 qubits; every pass from 31), so
+// no pass reads a stored one.  Measured per pass at 28 qubits (same box,
+// microseconds): contiguous add on 2^12 tiles 1005 against 1068 for the old
+// middle group (bits 12-19, 2^13 tiles); fused pass of bits 12-19 on 2^14
+// tiles, 512-byte rows, 1765 against 1981 for the old contiguous fused pass;
+// top group (bits 20-27) 2030 either way: 2902 against 3074 per term.  At 32
+// qubits (13 + 10 + 9 bits): 50.3 against 53.3 ms per term.  XCD-major order
+// helps the contiguous passes (1005 against 1053) and slows the strided fused
+// ones (1765 against 1810).
+template <typename R> inline std::vector<OrientSpec> action_plan(int n, bool diag_from_tables)
+{
+    std::vector<OrientSpec> S;
+    const bool otf_all = sizeof(R) == 4 && diag_from_tables && n >= OTF_NMIN;
+    if constexpr (sizeof(R) == 4) {
+        const bool st = stream_for<R>(n);
+        const bool kp = st && std::ldexp(12.0, n) <= 384.0 * (1 << 20);
+        if (n >= SPLIT_NMIN && n <= SPLIT_NMAX) {
+            const int h1 = (n - TB_NARROW + 1) / 2, h2 = n - TB_NARROW - h1;
+            const bool otf = diag_from_tables && n >= OTF_TOP_NMIN;
+            const TileCfg wide{TB_WIDE, NT_WIDE, st, 0, kp};
+            const TileCfg narrow{TB_NARROW, NT_NARROW, st, 0, kp};
+            S.push_back({{TB_WIDE - h1, TB_NARROW, h1}, wide, wide, otf, 0});
+            S.push_back({{0, 0, TB_NARROW}, narrow, narrow, false, 1});
+            S.push_back({{Cfg<R>::TB - h2, TB_NARROW + h1, h2}, {Cfg<R>::TB, Cfg<R>::NT, st, 0, kp},
+                         {Cfg<R>::TB, NT_MID, st, 0, kp}, otf, 0});
+            return S;
+        }
+        if (n == 32) {
+            const TileCfg wide{TB_WIDE, NT_WIDE, st, 0, false};
+            const TileCfg contig{Cfg<R>::TB, Cfg<R>::NT, st, 0, false};
+            S.push_back({{TB_WIDE - 10, Cfg<R>::TB, 10}, wide, wide, otf_all, 1});
+            S.push_back({{0, 0, Cfg<R>::TB}, contig, contig, false, 1});
+            S.push_back({{TB_WIDE - 9, Cfg<R>::TB + 10, 9}, wide, wide, otf_all, 0});
+            return S;
+        }
+    }
+    // otherwise the size's tile configuration: the contiguous orientation first
+    const TileCfg cfg = tile_cfg_for<R>(n);
+    const std::vector<PassPlan> plan = plan_passes(n, cfg.tb, Cfg<R>::LMIN, cfg.tb0);
+    const bool xcd_shape = sizeof(R) == 4 && ((cfg.tb == Cfg<R>::TB && cfg.nt == Cfg<R>::NT) || cfg.tb == TB_WIDE);
+    for (const PassPlan &pl : plan)
+        S.push_back({pl, pass_cfg<R>(cfg, pl, PM_FUSED), pass_cfg<R>(cfg, pl, PM_ADD), otf_all,
+                     (xcd_shape && pl.g0 + pl.h < n) ? 1 : 0});
+    return S;
+}
+
+// Whether a call with this plan reads a stored diagonal: only START and FUSED
+// passes read it, and they run on the end orientations.
+inline bool plan_reads_diag(const std::vector<OrientSpec> &S)
+{
+    for (size_t o = 0; o < S.size(); ++o)
+        if ((o == 0 || o + 1 == S.size()) && !S[o].otf) return true;
+    return false;
+}
+
 #define QW_HIP(call)                                                                   \
     do {                                                                               \
         hipError_t e_ = (call);                                                        \

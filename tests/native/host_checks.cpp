@@ -31,13 +31,13 @@ using namespace qw;
 // flipped partners stay inside the tile, and the groups cover the n bits once.
 template <typename R> static void check_plans(int n, bool full)
 {
-    const TileCfg cfg = tile_cfg_for<R>(n);
-    const std::vector<PassPlan> plan = plan_passes(n, cfg.tb, Cfg<R>::LMIN, cfg.tb0);
+    const std::vector<OrientSpec> spec = action_plan<R>(n, true);
     uint64_t covered = 0;
-    for (size_t o = 0; o < plan.size(); ++o) {
-        const PassPlan &p = plan[o];
-        const TileCfg pc = pass_cfg<R>(cfg, p, o == 0 ? PM_START : PM_ADD);
-        CHECK(p.L + p.h <= pc.tb, "n=%d orientation %zu: %d + %d bits exceed the 2^%d tile", n, o, p.L, p.h, pc.tb);
+    for (size_t o = 0; o < spec.size(); ++o) {
+        const PassPlan &p = spec[o].pl;
+        for (const TileCfg &pc : {spec[o].fused, spec[o].add})
+            CHECK(p.L + p.h <= pc.tb, "n=%d orientation %zu: %d + %d bits exceed the 2^%d tile", n, o, p.L, p.h, pc.tb);
+        CHECK(!spec[o].otf || p.L + p.h == spec[o].fused.tb, "n=%d orientation %zu: on-the-fly tile not full", n, o);
         CHECK(p.h >= 1 && p.g0 + p.h <= n, "n=%d orientation %zu: group out of range", n, o);
         for (int j = 0; j < p.h; ++j) {
             const uint64_t bit = uint64_t(1) << (p.g0 + j);
