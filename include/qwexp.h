@@ -236,6 +236,27 @@ qw_status qw_expm_action_c128(int n, const double *diag, const double *h, const 
                               double tol, qw_method method,
                               void *workspace, size_t ws_bytes, void *stream, qw_info *info);
 
+/* Timing aid for choosing pass plans (not part of the action): one complex64
+ * hypercube pass of the Clenshaw recurrence (section II.D) over caller device
+ * buffers of 2^n complex64 amplitudes, with fixed coefficients, enqueued on
+ * stream; the caller times it (e.g. with events on the same stream).
+ *   mode        : 0 START (reads b1, psi, d), 1 ADD (b1, acc), 2 FUSED (b1, acc,
+ *                 psi, d; writes dst and dst2);
+ *   tb, nt      : tile of 2^tb amplitudes and nt threads: (12, 1024),
+ *                 (13, 1024), (13, 512) or (14, 1024);
+ *   on_the_fly  : START / FUSED rebuild the diagonal (d unused; (13, 512) and
+ *                 (14, 1024) tiles with L + h = tb);
+ *   L, g0, h    : the tile's L contiguous low bits and its h flipped bits
+ *                 g0 .. g0 + h - 1 (L = g0 = 0: the contiguous orientation);
+ *   xcd_order   : blocks take tiles in XCD-major order;
+ *   workspace   : device, qw_workspace_bytes(n, 64, 1) bytes (tables of the
+ *                 rebuilt diagonal, cleared here).
+ * Outputs may alias inputs as in the action (dst = acc, dst2 = b1).  QW_EINVAL
+ * for a shape or orientation the kernels do not have. */
+qw_status qw_time_pass_c64(int n, int mode, int tb, int nt, int on_the_fly, int L, int g0, int h, int xcd_order,
+                           const void *b1, const void *acc, void *dst, void *dst2, const void *psi,
+                           const float *d, void *workspace, size_t ws_bytes, void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * action as qw_expm_action_c64, same kernels and results, with no workspace

@@ -970,6 +970,71 @@ qw_status qw_poly_action_c128(int n, const double *diag, const double *h, const 
                               stream, info);
 }
 
+// One complex64 hypercube pass of a chosen tile shape over caller buffers, for
+// timing the shapes a plan is chosen from (the coefficients are fixed, so the
+// output is not a Clenshaw term of anything).
+qw_status qw_time_pass_c64(int n, int mode, int tb, int nt, int on_the_fly, int L, int g0, int h, int xcd_order,
+                           const void *b1, const void *acc, void *dst, void *dst2, const void *psi, const float *d,
+                           void *workspace, size_t ws_bytes, void *stream)
+{
+    if (n < 14 || n > 32) { set_error("n must be in 14..32"); return QW_EINVAL; }
+    if (mode != PM_START && mode != PM_ADD && mode != PM_FUSED) { set_error("mode: 0 start, 1 add, 2 fused"); return QW_EINVAL; }
+    const bool shape = (tb == TB_NARROW && nt == NT_NARROW) || (tb == Cfg<float>::TB && (nt == NT_MID || nt == Cfg<float>::NT)) ||
+                       (tb == TB_WIDE && nt == NT_WIDE);
+    if (!shape) { set_error("tile shape must be (12, 1024), (13, 1024), (13, 512) or (14, 1024)"); return QW_EINVAL; }
+    const bool otf = on_the_fly != 0 && mode != PM_ADD;
+    if (otf && !((tb == Cfg<float>::TB && nt == Cfg<float>::NT) || tb == TB_WIDE)) {
+        set_error("the diagonal is rebuilt on (13, 512) and (14, 1024) tiles only");
+        return QW_EINVAL;
+    }
+    if (h < 1 || L < 0 || L + h > tb || (otf && L + h != tb) || g0 + h > n || !(g0 >= L || (g0 == 0 && L == 0))) {
+        set_error("bad orientation (L, g0, h) for this tile");
+        return QW_EINVAL;
+    }
+    const bool needs_d = (mode != PM_ADD) && !otf;
+    if (!b1 || !dst || (mode != PM_START && !acc) || (mode == PM_FUSED && !dst2) || (mode != PM_ADD && !psi) ||
+        (needs_d && !d) || !workspace) {
+        set_error("missing buffer for this mode");
+        return QW_EINVAL;
+    }
+    const WsLayout Lw = ws_layout(n, 64, true);
+    if (ws_bytes < Lw.total || (reinterpret_cast<uintptr_t>(workspace) & 255)) {
+        set_error("workspace: qw_workspace_bytes(n, 64, 1) bytes, 256-byte aligned");
+        return QW_EINVAL;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    double *qt = reinterpret_cast<double *>(ws + Lw.qt), *ft = reinterpret_cast<double *>(ws + Lw.ft);
+    const uint64_t ntiles = (uint64_t(1) << n) >> (L + h);
+    if (otf) {
+        hipLaunchKernelGGL(k_fill_zero<0>, dim3(64), dim3(256), 0, s, qt, (uint64_t)(1 << TB_WIDE));
+        hipLaunchKernelGGL(k_fill_zero<0>, dim3(grid_for(ntiles * TILE_FIELDS, 256, 1 << 16)), dim3(256), 0, s, ft,
+                           ntiles * TILE_FIELDS);
+    }
+    PassArgs<float> a{};
+    a.b1 = static_cast<const float2 *>(b1);
+    a.acc = static_cast<const float2 *>(mode == PM_START ? nullptr : acc);
+    a.dst = static_cast<float2 *>(dst);
+    a.dst2 = static_cast<float2 *>(dst2);
+    a.psi = static_cast<const float2 *>(psi);
+    a.d = d;
+    a.Qt = qt;
+    a.Ft = otf ? ft : nullptr;
+    a.g = 0.01f;
+    a.scale = 2.f;
+    a.scale2 = 2.f;
+    a.cr = 0.1f;
+    a.ci = 0.2f;
+    a.n = n;
+    a.L = L;
+    a.g0 = g0;
+    a.h = h;
+    a.xcd_order = xcd_order ? 1 : 0;
+    launch_pass<float>(a, mode, otf, ntiles, s, TileCfg{tb, nt, true, 0, false});
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
 // Host-only: the pass sequence for degree K and P orientations as (mode,
 // orientation, k, fin) quadruples; returns the number of passes (or the
 // capacity needed when cap is too small).
