@@ -233,21 +233,26 @@ def batched_leg(torch, qw, synth, np):
     import tempfile
     cache = os.path.join(tempfile.gettempdir(), f"qwexp_batched_tune_{os.getpid()}.txt")
     with torch.cuda.stream(stream):
+        # default schedule (first call captures its graph, the second replays it)
+        qw.expm_action_batched(b, stream=stream, sched={})
+        dflt = qw.expm_action_batched(b, stream=stream, sched={}, timing=1)
         t0 = time.perf_counter()
-        best_wave = qw.batched_tune(b, cache, stream=stream)     # autotuner: picks the wave size
+        best = qw.batched_tune(b, cache, stream=stream)     # autotuner: tile classes, on-chip limit, waves
         tune_s = time.perf_counter() - t0
-        qw.expm_action_batched(b, stream=stream, tune_cache=cache)
+        first = qw.expm_action_batched(b, stream=stream, tune_cache=cache)
         stream.synchronize()
         t0 = time.perf_counter()
         info = qw.expm_action_batched(b, stream=stream, timing=1, tune_cache=cache)
         stream.synchronize()
         wall = time.perf_counter() - t0
-        one = qw.expm_action_batched(b, stream=stream, timing=1, wave_bytes=0)
     os.remove(cache)
     out = {"instances": 256, "amp_terms": info["amp_terms"], "ms": wall * 1e3, "loop_ms": info["loop_ms"],
            "setup_ms": info["setup_ms"], "value": info["amp_terms"] / wall, "unit": UNIT,
            "launches": info["launches"], "waves": info["waves"], "small": info["small_count"],
-           "tuned_wave_bytes": best_wave, "tune_s": tune_s, "one_wave_loop_ms": one["loop_ms"]}
+           "tuned_schedule": best, "tile_class_used": info["tile_class"], "class_count": info["class_count"],
+           "tune_s": tune_s, "graph_ms_first_call": first["graph_ms"], "graph_cached": info["graph_cached"],
+           "default_schedule_loop_ms": dflt["loop_ms"],
+           "tuned_gain": dflt["loop_ms"] / info["loop_ms"]}
     for prec, dt in ((128, torch.complex128), (64, torch.complex64)):
         t0 = time.perf_counter()
         for i, ins in enumerate(insts):

@@ -285,12 +285,34 @@ typedef struct {
     int64_t off_hJ, off_psi, off_out;
 } qw_batch_item;
 
+/* Schedule of a batched call (what qw_batched_tune_c64 chooses). */
+typedef struct {
+    long long wave_bytes;       /* working-set cap of a wave of multi-pass instances
+                                   (20 B per amplitude; 0: all in one wave)       */
+    int onchip_nmax;            /* instances with n <= this (12 or 13; 0 = 13) run
+                                   whole in one workgroup                          */
+    int concurrent;             /* 1: that launch runs on a side stream of default
+                                   priority, beside the multi-pass launches        */
+    signed char tile_class[23]; /* per n (index n), multi-pass instances: 0 = 2^13-
+                                   amplitude tiles, 1024 threads; 1 = 2^12, 1024
+                                   threads (13 <= n <= 20); 2 = 2^13, 512 threads;
+                                   -1 = default (1 for n = 13, else 0)             */
+} qw_batch_sched;
+
 typedef struct {
     int timing;         /* in: nonzero times setup and recurrence with HIP events */
     int count, small_count, large_count, max_K, launches, waves;
     long long amp_terms;   /* sum over instances of 2^n K                         */
     long long wave_bytes;  /* working-set cap per wave used (0: one wave)         */
-    float setup_ms, loop_ms;
+    float setup_ms;        /* (timing) bound, diagonals, coefficients, uploads    */
+    float loop_ms;         /* (timing) the recurrence launches (graph replay)     */
+    int onchip_nmax, concurrent;   /* the schedule used                           */
+    int graph_cached;      /* 1: the instantiated graph of an earlier call with the
+                              same launch sequence and workspace was replayed     */
+    float graph_ms;        /* host time to capture and instantiate the graph (0
+                              when cached); not part of setup_ms or loop_ms       */
+    int class_count[3];    /* multi-pass instances per tile class                 */
+    signed char tile_class[23];   /* class used per n (-1: none / one workgroup)  */
 } qw_batch_info;
 
 /* Workspace bytes for qw_expm_action_batched_c64 (0 if the batch is invalid). */
@@ -298,10 +320,12 @@ size_t qw_batched_workspace_bytes_c64(const qw_batch_item *items, int count, con
 
 /* psi_out_i = exp(-i t_i (H_P,i + gamma_i sum_j X_j)) psi_in_i for every item,
  * complex64, each instance with its own spectral shift, bound and coefficients
- * (degree chosen for its own tol).  Instances with n <= 13 run in one
- * persistent on-chip launch; larger ones in grouped two-pass launches captured
- * into a HIP graph (eager launches when stream is NULL), in waves whose size is
- * read from the tune file tune_cache (may be NULL: one wave).
+ * (degree chosen for its own tol).  Instances with n <= 13 (or 12) run in one
+ * persistent on-chip launch; larger ones in grouped two-pass launches (one per
+ * tile class and step) captured into a HIP graph (eager launches when stream
+ * is NULL), which later calls with the same launch sequence and workspace
+ * replay without capturing again (a few graphs are kept per process).  The
+ * schedule comes from the tune file tune_cache (may be NULL: the default).
  *   items : host array of count items; hJ_pool: host doubles;
  *   psi_pool / out_pool : device complex64 pools (16-byte aligned; output
  *   ranges must not overlap each other or any input range);
@@ -312,18 +336,25 @@ qw_status qw_expm_action_batched_c64(const qw_batch_item *items, int count, cons
                                      void *workspace, size_t ws_bytes, const char *tune_cache,
                                      void *stream, qw_batch_info *info);
 
-/* Same with an explicit schedule: wave_bytes caps the working set of a wave
- * (0 = all large instances in one wave); use_graph = 0 launches eagerly. */
+/* Same with an explicit schedule (sched may be NULL: the default);
+ * use_graph = 0 launches eagerly.  QW_EINVAL for a tile class that cannot hold
+ * a size of the batch. */
 qw_status qw_expm_action_batched_c64_sched(const qw_batch_item *items, int count, const double *hJ_pool,
                                            const void *psi_pool, void *out_pool, qw_method method,
-                                           void *workspace, size_t ws_bytes, long long wave_bytes,
+                                           void *workspace, size_t ws_bytes, const qw_batch_sched *sched,
                                            int use_graph, void *stream, qw_batch_info *info);
 
-/* Autotuner: runs the batch with several wave sizes, keeps the fastest and
- * appends "<size signature> <wave bytes> <ms>" to the text file tune_cache. */
+/* Autotuner (section III.A's batching, with tile shapes chosen per size):
+ * times the batch under candidate schedules -- the tile class of each size
+ * bucket (13-16, 17-18, 19-20, 21-22 qubits) in turn, the one-workgroup limit,
+ * the side-stream launch, wave sizes of 512 / 256 / 128 MB -- keeping a change
+ * when it is faster (HIP events around the recurrence, graph built first);
+ * writes the best to *best (may be NULL) and appends "<size signature>
+ * wave=<bytes> onchip=<n> conc=<0|1> classes=<per n 1..22> ms=<time>" to the
+ * text file tune_cache (may be NULL). */
 qw_status qw_batched_tune_c64(const qw_batch_item *items, int count, const double *hJ_pool,
                               const void *psi_pool, void *out_pool, void *workspace, size_t ws_bytes,
-                              const char *tune_cache, void *stream, long long *best_wave_bytes);
+                              const char *tune_cache, void *stream, qw_batch_sched *best);
 
 /* ---- anneal energy and gradient ----------------------------------------- */
 

@@ -414,10 +414,36 @@ class BatchInfo(ctypes.Structure):
     _fields_ = [("timing", ctypes.c_int), ("count", ctypes.c_int), ("small_count", ctypes.c_int),
                 ("large_count", ctypes.c_int), ("max_K", ctypes.c_int), ("launches", ctypes.c_int),
                 ("waves", ctypes.c_int), ("amp_terms", ctypes.c_longlong), ("wave_bytes", ctypes.c_longlong),
-                ("setup_ms", ctypes.c_float), ("loop_ms", ctypes.c_float)]
+                ("setup_ms", ctypes.c_float), ("loop_ms", ctypes.c_float), ("onchip_nmax", ctypes.c_int),
+                ("concurrent", ctypes.c_int), ("graph_cached", ctypes.c_int), ("graph_ms", ctypes.c_float),
+                ("class_count", ctypes.c_int * 3), ("tile_class", ctypes.c_byte * 23)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["class_count"] = list(self.class_count)
+        d["tile_class"] = {n: int(self.tile_class[n]) for n in range(23) if self.tile_class[n] >= 0}
+        return d
+
+
+class BatchSched(ctypes.Structure):
+    """Schedule of a batched call (qw_batch_sched): wave_bytes, onchip_nmax,
+    concurrent and a tile class per size (-1 = default)."""
+    _fields_ = [("wave_bytes", ctypes.c_longlong), ("onchip_nmax", ctypes.c_int), ("concurrent", ctypes.c_int),
+                ("tile_class", ctypes.c_byte * 23)]
+
+    @staticmethod
+    def make(wave_bytes: int = 0, onchip_nmax: int = 13, concurrent: bool = False, tile_class: dict | None = None):
+        S = BatchSched()
+        S.wave_bytes, S.onchip_nmax, S.concurrent = int(wave_bytes), int(onchip_nmax), 1 if concurrent else 0
+        for n in range(23):
+            S.tile_class[n] = -1
+        for n, c in (tile_class or {}).items():
+            S.tile_class[int(n)] = int(c)
+        return S
+
+    def as_dict(self) -> dict:
+        return {"wave_bytes": self.wave_bytes, "onchip_nmax": self.onchip_nmax, "concurrent": self.concurrent,
+                "tile_class": {n: int(self.tile_class[n]) for n in range(23) if self.tile_class[n] >= 0}}
 
 
 def _declare_batched(lib):
@@ -428,9 +454,9 @@ def _declare_batched(lib):
     lib.qw_expm_action_batched_c64.argtypes = [ctypes.POINTER(BatchItem), _i, _dp, _vp, _vp, _i, _vp, _sz,
                                                ctypes.c_char_p, _vp, ctypes.POINTER(BatchInfo)]
     lib.qw_expm_action_batched_c64_sched.argtypes = [ctypes.POINTER(BatchItem), _i, _dp, _vp, _vp, _i, _vp, _sz,
-                                                     ctypes.c_longlong, _i, _vp, ctypes.POINTER(BatchInfo)]
+                                                     ctypes.POINTER(BatchSched), _i, _vp, ctypes.POINTER(BatchInfo)]
     lib.qw_batched_tune_c64.argtypes = [ctypes.POINTER(BatchItem), _i, _dp, _vp, _vp, _vp, _sz,
-                                        ctypes.c_char_p, _vp, ctypes.POINTER(ctypes.c_longlong)]
+                                        ctypes.c_char_p, _vp, ctypes.POINTER(BatchSched)]
     lib._qw_batched_declared = True
 
 
@@ -481,36 +507,46 @@ class Batch:
 
 
 def expm_action_batched(batch: Batch, method: str = "cheb", tune_cache: str | None = None, stream=None,
-                        timing: int = 0, wave_bytes: int | None = None, use_graph: bool = True) -> dict:
+                        timing: int = 0, wave_bytes: int | None = None, use_graph: bool = True,
+                        sched: BatchSched | dict | None = None) -> dict:
     """Run every instance of the batch; outputs land in batch.out_pool.  With
-    wave_bytes / use_graph given the schedule is explicit, otherwise it comes
-    from the tune file (or one wave)."""
+    sched (a BatchSched or the keyword dict of BatchSched.make), wave_bytes or
+    use_graph=False the schedule is explicit, otherwise it comes from the tune
+    file (or the default)."""
     L = lib()
     _declare_batched(L)
     info = BatchInfo()
     info.timing = int(timing)
     args = (batch.items, batch.count, batch.hJ.ctypes.data_as(_dp), _vp(batch.psi_pool.data_ptr()),
             _vp(batch.out_pool.data_ptr()), _METHODS[method], _vp(batch.ws_ptr()), batch.ws_bytes)
-    if wave_bytes is None and use_graph:
+    if sched is None and wave_bytes is None and use_graph:
         st = L.qw_expm_action_batched_c64(*args, tune_cache.encode() if tune_cache else None, _stream_ptr(stream),
                                           ctypes.byref(info))
     else:
-        st = L.qw_expm_action_batched_c64_sched(*args, int(wave_bytes or 0), 1 if use_graph else 0,
+        if isinstance(sched, dict):
+            sched = BatchSched.make(**sched)
+        if sched is None:
+            sched = BatchSched.make(wave_bytes=int(wave_bytes or 0))
+        elif wave_bytes is not None:
+            sched.wave_bytes = int(wave_bytes)
+        st = L.qw_expm_action_batched_c64_sched(*args, ctypes.byref(sched), 1 if use_graph else 0,
                                                 _stream_ptr(stream), ctypes.byref(info))
     _check(st)
     return info.as_dict()
 
 
-def batched_tune(batch: Batch, tune_cache: str, stream=None) -> int:
-    """Time the candidate wave sizes on this batch and append the best to tune_cache."""
+def batched_tune(batch: Batch, tune_cache: str | None, stream=None) -> dict:
+    """Search the schedule of this batch (tile class per size bucket, the
+    one-workgroup limit, the side-stream launch, the wave size), append the
+    best to tune_cache and return it as a dict."""
     L = lib()
     _declare_batched(L)
-    best = ctypes.c_longlong(0)
+    best = BatchSched()
     _check(L.qw_batched_tune_c64(batch.items, batch.count, batch.hJ.ctypes.data_as(_dp),
                                  _vp(batch.psi_pool.data_ptr()), _vp(batch.out_pool.data_ptr()),
-                                 _vp(batch.ws_ptr()), batch.ws_bytes, tune_cache.encode(), _stream_ptr(stream),
-                                 ctypes.byref(best)))
-    return int(best.value)
+                                 _vp(batch.ws_ptr()), batch.ws_bytes, tune_cache.encode() if tune_cache else None,
+                                 _stream_ptr(stream), ctypes.byref(best)))
+    return best.as_dict()
 
 
 # ------------------------------------------------------------------ anneal gradient

@@ -20,8 +20,11 @@
 // the couplings of every instance (section III.A: only the couplings are sent).
 #include "qw_kernels.h"
 
+#include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <fstream>
+#include <mutex>
 #include <numeric>
 #include <sstream>
 
@@ -132,36 +135,31 @@ __global__ void __launch_bounds__(256) k_minmax_instances(const BatchDesc *D, co
     }
 }
 
-// b1 = c_K psi over one 2^13 tile of a large instance (b_{K+1} = 0 is never
-// read: the first pass takes no accumulator).
-__global__ void __launch_bounds__(256) k_init_batched(const BatchDesc *D, const int2 *tiles)
-{
-    const int2 tt = tiles[blockIdx.x];
-    const BatchDesc &b = D[tt.x];
-    const float2 cK = b.coef[b.K];
-    const uint64_t base = (uint64_t)tt.y << Cfg<float>::TB;
-    for (uint32_t e = threadIdx.x; e < (1u << Cfg<float>::TB); e += blockDim.x) {
-        const float2 p = b.psi[base + e];
-        b.B1[base + e] = make_float2(cK.x * p.x - cK.y * p.y, cK.x * p.y + cK.y * p.x);
-    }
-}
-
 // Global step `step` of the fused two-orientation schedule for the tile
-// (instance, t) of this block.  Every instance with 14 <= n <= 22 runs
+// (instance, t) of this block.  Every instance of the multi-pass class runs
 // K + 1 passes: step 0 starts term K-1 in the low orientation (MODE START);
 // step j (1 <= j < K) completes term K-j and starts term K-j-1 in one fused
 // pass; step K completes term 0 and writes the output (MODE ADD).  The
-// orientation alternates (even steps: the low 13 bits, odd steps: the n-13
+// orientation alternates (even steps: the low TB bits, odd steps: the n - TB
 // high bits), so it is the same for every active instance of a step; the
-// host launches the fused and the final instances of a step separately.
-// 1024 threads per workgroup (16 waves, one workgroup per CU): the per-instance
-// arguments live in vector registers here, so fewer amplitudes per thread keep
-// the fused pass free of spills (capped at 64 registers for two workgroups per
-// CU it spilled and ran 6 % slower).  STREAM: the b vectors carry the
-// non-temporal hint and psi and the diagonal stay cacheable, for waves whose
-// vectors exceed the memory-side cache (256 instances of 12..22 qubits, 7.7 GB:
-// 1093 -> 1020 ms; the hint on psi and the diagonal as well: 1043 ms).
-static constexpr int BNT = 1024;
+// host launches the fused and the final instances of a step separately.  The
+// Clenshaw start b_K = c_K psi is folded into the loads: steps 0 and 1 read
+// psi scaled by c_K as b_{k+1}, so b_K is never stored.
+//
+// Tile classes (chosen per instance size by the tuner): MID = 2^13 tiles with
+// 1024 threads (8 amplitudes per thread; the per-instance arguments live in
+// vector registers, so fewer amplitudes per thread keep the fused pass free
+// of spills), NARROW = 2^12 tiles with 1024 threads (n <= 20), WIDE_T = 2^13
+// tiles with 512 threads.  STREAM: the b vectors carry the non-temporal hint
+// and psi and the diagonal stay cacheable, for waves whose vectors exceed the
+// memory-side cache (256 instances of 12..22 qubits, 7.7 GB: 1093 -> 1020 ms;
+// the hint on psi and the diagonal as well: 1043 ms).
+enum BatchClass { BC_MID = 0, BC_NARROW = 1, BC_WIDE_T = 2, BC_COUNT = 3 };
+template <int C> struct ClassShape;
+template <> struct ClassShape<BC_MID> { static constexpr int TB = 13, NT = 1024; };
+template <> struct ClassShape<BC_NARROW> { static constexpr int TB = 12, NT = 1024; };
+template <> struct ClassShape<BC_WIDE_T> { static constexpr int TB = 13, NT = 512; };
+inline int class_tb(int c) { return c == BC_NARROW ? 12 : 13; }
 
 // c_k of an instance, read through a global pointer (one value for the block)
 __device__ __forceinline__ float2 coef_at(const float2 *coef, int k)
@@ -170,11 +168,11 @@ __device__ __forceinline__ float2 coef_at(const float2 *coef, int k)
     return make_float2(c[0], c[1]);
 }
 
-template <bool HIGH, int MODE, bool STREAM = false>
-__global__ void __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(4)))
+template <int CLS, bool HIGH, int MODE, bool STREAM = false>
+__global__ void __launch_bounds__(ClassShape<CLS>::NT) __attribute__((amdgpu_waves_per_eu(4)))
 k_pass_batched(const BatchDesc *D, const int2 *tiles, int step)
 {
-    constexpr int TB = Cfg<float>::TB, NT = BNT;
+    constexpr int TB = ClassShape<CLS>::TB, NT = ClassShape<CLS>::NT;
     __shared__ float2 lds[1 << TB];
     const int2 tt = wave_uniform(tiles[blockIdx.x]);
     const BatchDesc b = wave_uniform(D[tt.x]);
@@ -183,6 +181,14 @@ k_pass_batched(const BatchDesc *D, const int2 *tiles, int step)
     float2 *Y = swapped ? b.B1 : b.B2;
     PassArgs<float> a{};
     a.b1 = X;
+    if (step <= 1) {
+        // b_{k+1} = b_K = c_K psi (b_K itself is never stored)
+        const float2 cK = coef_at(b.coef, b.K);
+        a.b1 = b.psi;
+        a.b1_scaled = 1;
+        a.b1r = cK.x;
+        a.b1i = cK.y;
+    }
     a.psi = b.psi;
     a.d = b.d;
     a.g = b.g;
@@ -232,6 +238,45 @@ k_pass_batched(const BatchDesc *D, const int2 *tiles, int step)
 
 static constexpr int BATCH_MAXN = 22;
 
+// Schedule of a batch: the largest size run whole in one workgroup, the tile
+// class of every larger size, the working-set cap of a wave, and whether the
+// one-workgroup launch runs beside the passes on a side stream.
+struct BatchSched {
+    long long wave_bytes = 0;
+    int onchip_nmax = Cfg<float>::TB;
+    int concurrent = 0;
+    signed char cls[BATCH_MAXN + 1];
+    BatchSched() { std::memset(cls, -1, sizeof(cls)); }
+};
+
+// Class actually used for a multi-pass instance of n qubits: the requested
+// one, else NARROW for n = 13 (the only class with two orientations there)
+// and MID above.
+static int class_for(const BatchSched &S, int n)
+{
+    const int c = S.cls[n];
+    if (c >= 0) return c;
+    return (n <= 13) ? (int)BC_NARROW : (int)BC_MID;
+}
+
+static qw_status validate_sched(const BatchSched &S)
+{
+    if (S.wave_bytes < 0) { set_error("wave_bytes must be >= 0"); return QW_EINVAL; }
+    if (S.onchip_nmax != 12 && S.onchip_nmax != 13) { set_error("onchip_nmax must be 12 or 13"); return QW_EINVAL; }
+    for (int n = 1; n <= BATCH_MAXN; ++n) {
+        const int c = S.cls[n];
+        if (c < -1 || c >= BC_COUNT) { set_error("tile class must be -1, 0, 1 or 2"); return QW_EINVAL; }
+        if (n <= S.onchip_nmax || c < 0) continue;
+        // two orientations of at most TB bits each, the high one with >= 4 passenger bits
+        const int tb = class_tb(c);
+        if (n <= tb || n - tb > tb - Cfg<float>::LMIN) {
+            set_error("tile class " + std::to_string(c) + " cannot hold " + std::to_string(n) + " qubits");
+            return QW_EINVAL;
+        }
+    }
+    return QW_OK;
+}
+
 struct BatchPlan {
     size_t total = 0;
     size_t off_desc, off_etiles, off_tiles, off_part, off_emm, off_hj, off_q, off_coef, off_items, off_order;
@@ -251,6 +296,9 @@ static int degree_bound(const qw_batch_item &it, const double *hJ)
     return bessel_cutoff(std::fabs(it.t) * rmax * 1.01 + 1.0) + 2;
 }
 
+// Workspace layout; it does not depend on the schedule: every instance of
+// n >= 13 has its two work vectors and room for its tiles in the smallest
+// tile class.
 static BatchPlan plan_batch(const qw_batch_item *items, int count, const double *hJ)
 {
     BatchPlan P;
@@ -263,10 +311,10 @@ static BatchPlan plan_batch(const qw_batch_item *items, int count, const double 
         const int n = items[i].n;
         const size_t N = size_t(1) << n;
         P.n_etiles += (n > LB_TAB) ? (int)(N >> LB_TAB) : 1;
-        if (n > Cfg<float>::TB) {
+        if (n >= 13) {
             P.off_b1[i] = take(N * 8);
             P.off_b2[i] = take(N * 8);
-            P.n_tiles += (int)(N >> Cfg<float>::TB);
+            P.n_tiles += (int)(N >> 12);
         } else {
             P.off_b1[i] = P.off_b2[i] = size_t(-1);
         }
@@ -311,22 +359,6 @@ static qw_status validate_batch(const qw_batch_item *items, int count, const dou
     return QW_OK;
 }
 
-// Wave size in bytes from the tune file (0 = all large instances together).
-static size_t read_tuned_wave(const char *path, const std::string &sig)
-{
-    if (!path) return 0;
-    std::ifstream f(path);
-    std::string line;
-    size_t best = 0;
-    while (std::getline(f, line)) {
-        std::istringstream is(line);
-        std::string s;
-        size_t w;
-        if (is >> s >> w && s == sig) best = w;
-    }
-    return best;
-}
-
 static std::string batch_signature(const qw_batch_item *items, int count)
 {
     // size histogram: the schedule depends on the sizes only
@@ -339,19 +371,163 @@ static std::string batch_signature(const qw_batch_item *items, int count)
     return os.str();
 }
 
+// Tune file: one line per tuning, "<signature> wave=<bytes> onchip=<n>
+// conc=<0|1> classes=<one digit per n = 1..22, '-' = default> ms=<time>"; the
+// last line of the batch's signature wins.
+static std::string sched_fields(const BatchSched &S)
+{
+    std::ostringstream os;
+    os << "wave=" << S.wave_bytes << " onchip=" << S.onchip_nmax << " conc=" << S.concurrent << " classes=";
+    for (int n = 1; n <= BATCH_MAXN; ++n) os << (S.cls[n] < 0 ? '-' : (char)('0' + S.cls[n]));
+    return os.str();
+}
+
+static bool read_tuned_sched(const char *path, const std::string &sig, BatchSched *out)
+{
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string s, tok;
+        if (!(is >> s) || s != sig) continue;
+        BatchSched S;
+        bool ok = true;
+        while (is >> tok) {
+            const size_t eq = tok.find('=');
+            if (eq == std::string::npos) { ok = false; break; }
+            const std::string k = tok.substr(0, eq), v = tok.substr(eq + 1);
+            if (k == "wave") S.wave_bytes = std::atoll(v.c_str());
+            else if (k == "onchip") S.onchip_nmax = std::atoi(v.c_str());
+            else if (k == "conc") S.concurrent = std::atoi(v.c_str());
+            else if (k == "classes") {
+                if ((int)v.size() != BATCH_MAXN) { ok = false; break; }
+                for (int n = 1; n <= BATCH_MAXN; ++n) S.cls[n] = (v[n - 1] == '-') ? -1 : (signed char)(v[n - 1] - '0');
+            }
+        }
+        if (ok && validate_sched(S) == QW_OK) {
+            *out = S;
+            found = true;
+        }
+    }
+    return found;
+}
+
+// One launch of a batched call.
+struct BLaunch {
+    int onchip;      // 1: the one-workgroup launch over the small instances
+    int cls, mode, high, stream_hint;
+    unsigned grid;
+    const int2 *tiles;
+    int step;
+};
+
+template <int C> static void launch_class(const BLaunch &L, const BatchDesc *dD, hipStream_t s)
+{
+    const dim3 g(L.grid), b(ClassShape<C>::NT);
+    const int st = L.step;
+    const int2 *t = L.tiles;
+    if (L.stream_hint) {
+        if (L.mode == PM_START) hipLaunchKernelGGL((k_pass_batched<C, false, PM_START, true>), g, b, 0, s, dD, t, st);
+        else if (L.mode == PM_FUSED && L.high) hipLaunchKernelGGL((k_pass_batched<C, true, PM_FUSED, true>), g, b, 0, s, dD, t, st);
+        else if (L.mode == PM_FUSED) hipLaunchKernelGGL((k_pass_batched<C, false, PM_FUSED, true>), g, b, 0, s, dD, t, st);
+        else if (L.high) hipLaunchKernelGGL((k_pass_batched<C, true, PM_ADD, true>), g, b, 0, s, dD, t, st);
+        else hipLaunchKernelGGL((k_pass_batched<C, false, PM_ADD, true>), g, b, 0, s, dD, t, st);
+    } else {
+        if (L.mode == PM_START) hipLaunchKernelGGL((k_pass_batched<C, false, PM_START>), g, b, 0, s, dD, t, st);
+        else if (L.mode == PM_FUSED && L.high) hipLaunchKernelGGL((k_pass_batched<C, true, PM_FUSED>), g, b, 0, s, dD, t, st);
+        else if (L.mode == PM_FUSED) hipLaunchKernelGGL((k_pass_batched<C, false, PM_FUSED>), g, b, 0, s, dD, t, st);
+        else if (L.high) hipLaunchKernelGGL((k_pass_batched<C, true, PM_ADD>), g, b, 0, s, dD, t, st);
+        else hipLaunchKernelGGL((k_pass_batched<C, false, PM_ADD>), g, b, 0, s, dD, t, st);
+    }
+}
+
+// Side stream of a device (default priority), for the one-workgroup launch
+// beside the passes; created once, kept until the process ends.
+static qw_status side_stream(hipStream_t *out)
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    QW_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) { set_error("device index out of range"); return QW_EINVAL; }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev]) QW_HIP(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+    *out = streams[dev];
+    return QW_OK;
+}
+
+// Enqueues the launches on s (captured or not).  The one-workgroup launch goes
+// first; with `side` it runs on the side stream between a fork and a join
+// event, so it overlaps the passes.
+static qw_status replay(const std::vector<BLaunch> &Ls, const BatchDesc *dD, const OnchipItem<float> *ditems,
+                        const int *dorder, int nsmall, hipStream_t s, hipStream_t side, hipEvent_t fork,
+                        hipEvent_t join)
+{
+    bool joined = true;
+    for (const BLaunch &L : Ls) {
+        if (L.onchip) {
+            hipStream_t os = s;
+            if (side) {
+                QW_HIP(hipEventRecord(fork, s));
+                QW_HIP(hipStreamWaitEvent(side, fork, 0));
+                os = side;
+                joined = false;
+            }
+            hipLaunchKernelGGL((k_onchip<float, Cfg<float>::TB, ONCHIP_NT>), dim3(L.grid), dim3(ONCHIP_NT), 0, os,
+                               ditems, dorder, nsmall);
+            if (side) QW_HIP(hipEventRecord(join, side));
+            continue;
+        }
+        if (L.cls == BC_NARROW) launch_class<BC_NARROW>(L, dD, s);
+        else if (L.cls == BC_WIDE_T) launch_class<BC_WIDE_T>(L, dD, s);
+        else launch_class<BC_MID>(L, dD, s);
+    }
+    if (!joined) QW_HIP(hipStreamWaitEvent(s, join, 0));
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
+// Instantiated graphs of recent calls, keyed by the device, the workspace and
+// the exact launch sequence (which fixes every kernel argument: descriptors
+// and tile tables are re-uploaded into the same workspace places before each
+// replay).  At most GRAPH_CACHE entries; the oldest is destroyed first.
+static constexpr size_t GRAPH_CACHE = 4;
+struct GraphEntry {
+    int dev;
+    std::string key;
+    hipGraphExec_t exec;
+};
+static std::mutex g_graph_mu;
+static std::vector<GraphEntry> g_graphs;
+
+static std::string launch_key(const std::vector<BLaunch> &Ls, const void *ws, int conc)
+{
+    std::ostringstream os;
+    os << ws << ':' << conc;
+    for (const BLaunch &L : Ls)
+        os << ';' << L.onchip << ',' << L.cls << ',' << L.mode << ',' << L.high << ',' << L.stream_hint << ','
+           << L.grid << ',' << static_cast<const void *>(L.tiles) << ',' << L.step;
+    return os.str();
+}
+
 struct BatchRun {
     std::vector<int> large, small;   // instance indices
     std::vector<int> K;
     int maxK = 0;
     long long amp_terms = 0;
     int launches = 0, waves = 0;
+    int class_count[BC_COUNT] = {0, 0, 0};
 };
 
 static qw_status batched_impl(const qw_batch_item *items, int count, const double *hJ, const void *psi_pool,
-                              void *out_pool, int method, void *workspace, size_t ws_bytes, size_t wave_bytes,
+                              void *out_pool, int method, void *workspace, size_t ws_bytes, const BatchSched &sch,
                               bool use_graph, hipStream_t s, qw_batch_info *info)
 {
     qw_status st = validate_batch(items, count, hJ);
+    if (st != QW_OK) return st;
+    st = validate_sched(sch);
     if (st != QW_OK) return st;
     if (method != QW_CHEB && method != QW_CF) { set_error("unknown method"); return QW_EINVAL; }
     if (!psi_pool || !out_pool || !workspace) { set_error("pools and workspace are required"); return QW_EINVAL; }
@@ -366,11 +542,18 @@ static qw_status batched_impl(const qw_batch_item *items, int count, const doubl
     const float2 *psi = static_cast<const float2 *>(psi_pool);
     float2 *out = static_cast<float2 *>(out_pool);
 
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // timing 0-2, fork 3, join 4
     const bool timing = info && info->timing;
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            for (int i = 0; i < 5; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } eg{ev};
     if (timing)
-        for (auto &e : ev) QW_HIP(hipEventCreate(&e));
-    struct EvGuard { hipEvent_t *e; ~EvGuard() { for (int i = 0; i < 3; ++i) if (e[i]) (void)hipEventDestroy(e[i]); } } eg{ev};
+        for (int i = 0; i < 3; ++i) QW_HIP(hipEventCreate(&ev[i]));
     if (timing) QW_HIP(hipEventRecord(ev[0], s));
 
     // couplings and descriptors (energy part)
@@ -451,7 +634,8 @@ static qw_status batched_impl(const qw_batch_item *items, int count, const doubl
             alpha.assign(1, 1.0);  // H = c I: exp(-itc) only
             K = 0;
         }
-        if (K == 0 && it.n > Cfg<float>::TB) {
+        const bool small = it.n <= sch.onchip_nmax;
+        if (K == 0 && !small) {
             // the grouped two-pass schedule needs one step: pad with c_1 = 0,
             // so the final step gives H~ 0 - 0 + c_0 psi
             alpha.resize(2);
@@ -475,7 +659,7 @@ static qw_status batched_impl(const qw_batch_item *items, int count, const doubl
         b.K = K;
         run.K[i] = K;
         run.amp_terms += (long long)K << it.n;
-        if (it.n <= Cfg<float>::TB) run.small.push_back(i);
+        if (small) run.small.push_back(i);
         else run.large.push_back(i);
         oitems[i] = OnchipItem<float>{b.psi, b.out, b.d, b.coef, b.g, b.pr, b.pi, it.n, K};
     }
@@ -495,17 +679,17 @@ static qw_status batched_impl(const qw_batch_item *items, int count, const doubl
     if (!run.small.empty())
         QW_HIP(hipMemcpyAsync(dorder, run.small.data(), run.small.size() * sizeof(int), hipMemcpyHostToDevice, s));
 
-    // large class: waves, each sorted by degree (descending) into the tile table
-    std::vector<int> L = run.large;
-    std::sort(L.begin(), L.end(), [&](int a, int b) { return run.K[a] > run.K[b]; });
+    // large class: waves (greedy in degree order up to wave_bytes of working
+    // set), inside a wave one degree-sorted tile table per tile class
+    std::vector<int> Lg = run.large;
+    std::sort(Lg.begin(), Lg.end(), [&](int a, int b) { return run.K[a] > run.K[b]; });
     std::vector<std::vector<int>> waves;
     {
-        // greedy packing in degree order up to wave_bytes of working set
         std::vector<int> cur;
         size_t cur_bytes = 0;
-        for (int i : L) {
+        for (int i : Lg) {
             const size_t bytes = (size_t(20)) << items[i].n;
-            if (wave_bytes && !cur.empty() && cur_bytes + bytes > wave_bytes) {
+            if (sch.wave_bytes && !cur.empty() && cur_bytes + bytes > (size_t)sch.wave_bytes) {
                 waves.push_back(cur);
                 cur.clear();
                 cur_bytes = 0;
@@ -517,107 +701,118 @@ static qw_status batched_impl(const qw_batch_item *items, int count, const doubl
     }
     std::vector<int2> tiles;
     tiles.reserve(P.n_tiles);
-    // prefix[j]: tiles of the instances still active at step j (K >= j)
-    struct WaveSched { int tile_begin; std::vector<int> prefix; bool stream; };
-    std::vector<WaveSched> sched;
-    for (auto &w : waves) {
-        std::sort(w.begin(), w.end(), [&](int a, int b) { return run.K[a] > run.K[b]; });
-        WaveSched ws_{(int)tiles.size(), {}, false};
-        std::vector<int> cum;
-        double wave_vec_bytes = 0.0;   // b1, b2, psi, out (8 B each) and the diagonal per amplitude
-        for (int i : w) {
-            wave_vec_bytes += std::ldexp(36.0, items[i].n);
-            const int nt = 1 << (items[i].n - Cfg<float>::TB);
-            for (int t = 0; t < nt; ++t) tiles.push_back(make_int2(i, t));
-            cum.push_back((int)tiles.size() - ws_.tile_begin);
-        }
-        ws_.stream = wave_vec_bytes > 384.0 * (1 << 20);
-        const int maxK = run.K[w.front()];
-        ws_.prefix.resize(maxK + 1);
-        size_t j = w.size();
-        for (int st = 0; st <= maxK; ++st) {
-            while (j > 0 && run.K[w[j - 1]] < st) --j;
-            ws_.prefix[st] = (j > 0) ? cum[j - 1] : 0;
-        }
-        sched.push_back(std::move(ws_));
-        run.maxK = std::max(run.maxK, maxK);
-    }
     int2 *dT = reinterpret_cast<int2 *>(ws + P.off_tiles);
+    std::vector<BLaunch> Ls;
+    if (!run.small.empty())
+        Ls.push_back({1, 0, 0, 0, 0, (unsigned)std::min<int>((int)run.small.size(), 512), nullptr, 0});
+    for (auto &w : waves) {
+        double wave_vec_bytes = 0.0;   // b1, b2, psi, out (8 B each) and the diagonal per amplitude
+        for (int i : w) wave_vec_bytes += std::ldexp(36.0, items[i].n);
+        const int hint = wave_vec_bytes > 384.0 * (1 << 20) ? 1 : 0;
+        struct ClassTable { int begin = 0; std::vector<int> prefix; };
+        ClassTable ct[BC_COUNT];
+        int wave_maxK = 0;
+        for (int c = 0; c < BC_COUNT; ++c) {
+            std::vector<int> mem;
+            for (int i : w)
+                if (class_for(sch, items[i].n) == c) mem.push_back(i);
+            if (mem.empty()) continue;
+            std::sort(mem.begin(), mem.end(), [&](int a, int b) { return run.K[a] > run.K[b]; });
+            ct[c].begin = (int)tiles.size();
+            std::vector<int> cum;
+            const int tb = class_tb(c);
+            for (int i : mem) {
+                const int nt = 1 << (items[i].n - tb);
+                for (int t = 0; t < nt; ++t) tiles.push_back(make_int2(i, t));
+                cum.push_back((int)tiles.size() - ct[c].begin);
+                run.class_count[c]++;
+            }
+            const int maxK = run.K[mem.front()];
+            wave_maxK = std::max(wave_maxK, maxK);
+            ct[c].prefix.resize(maxK + 1);
+            size_t j = mem.size();
+            for (int stp = 0; stp <= maxK; ++stp) {
+                while (j > 0 && run.K[mem[j - 1]] < stp) --j;
+                ct[c].prefix[stp] = (j > 0) ? cum[j - 1] : 0;
+            }
+        }
+        for (int stp = 0; stp <= wave_maxK; ++stp) {
+            const int high = stp & 1;
+            for (int c = 0; c < BC_COUNT; ++c) {
+                const std::vector<int> &pre = ct[c].prefix;
+                const int last = (int)pre.size() - 1;
+                if (stp > last) continue;
+                const int2 *t0 = dT + ct[c].begin;
+                if (stp == 0) {
+                    if (pre[0] > 0) Ls.push_back({0, c, PM_START, 0, hint, (unsigned)pre[0], t0, 0});
+                    continue;
+                }
+                // instances with K > stp fuse, those with K == stp finish
+                const int nfuse = (stp + 1 <= last) ? pre[stp + 1] : 0;
+                if (nfuse > 0) Ls.push_back({0, c, PM_FUSED, high, hint, (unsigned)nfuse, t0, stp});
+                if (pre[stp] - nfuse > 0)
+                    Ls.push_back({0, c, PM_ADD, high, hint, (unsigned)(pre[stp] - nfuse), t0 + nfuse, stp});
+            }
+        }
+        run.maxK = std::max(run.maxK, wave_maxK);
+    }
+    if ((int)tiles.size() > P.n_tiles) { set_error("internal: tile table overflow"); return QW_EINVAL; }
     if (!tiles.empty())
         QW_HIP(hipMemcpyAsync(dT, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, s));
     QW_HIP(hipStreamSynchronize(s));   // host staging buffers go out of scope below
-    if (timing) QW_HIP(hipEventRecord(ev[1], s));
 
-    if (!run.small.empty()) {
-        const int grid = std::min<int>((int)run.small.size(), 512);
-        hipLaunchKernelGGL((k_onchip<float, Cfg<float>::TB, ONCHIP_NT>), dim3(grid), dim3(ONCHIP_NT), 0, s,
-                           (const OnchipItem<float> *)ditems, (const int *)dorder, (int)run.small.size());
-        QW_HIP(hipGetLastError());
-        run.launches++;
+    hipStream_t side = nullptr;
+    const bool conc = sch.concurrent && !run.small.empty() && !Lg.empty();
+    if (conc) {
+        st = side_stream(&side);
+        if (st != QW_OK) return st;
+        QW_HIP(hipEventCreateWithFlags(&ev[3], hipEventDisableTiming));
+        QW_HIP(hipEventCreateWithFlags(&ev[4], hipEventDisableTiming));
     }
     if (s == nullptr) use_graph = false;   // the null stream cannot be captured
-    if (!sched.empty()) {
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        if (use_graph) QW_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (const WaveSched &w : sched) {
-            const int2 *wt = dT + w.tile_begin;
-            hipLaunchKernelGGL(k_init_batched, dim3(w.prefix[0]), dim3(256), 0, s, (const BatchDesc *)dD, wt);
-            run.launches++;
-            const int last = (int)w.prefix.size() - 1;   // = the largest K of the wave
-            auto launch = [&](int mode, bool high, int begin, int count, int st) {
-                if (count <= 0) return;
-                const dim3 g(count), bl(BNT);
-                const int2 *t0 = wt + begin;
-                const BatchDesc *dd = dD;
-                if (w.stream) {
-                    if (mode == PM_START) hipLaunchKernelGGL((k_pass_batched<false, PM_START, true>), g, bl, 0, s, dd, t0, st);
-                    else if (mode == PM_FUSED && high) hipLaunchKernelGGL((k_pass_batched<true, PM_FUSED, true>), g, bl, 0, s, dd, t0, st);
-                    else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass_batched<false, PM_FUSED, true>), g, bl, 0, s, dd, t0, st);
-                    else if (high) hipLaunchKernelGGL((k_pass_batched<true, PM_ADD, true>), g, bl, 0, s, dd, t0, st);
-                    else hipLaunchKernelGGL((k_pass_batched<false, PM_ADD, true>), g, bl, 0, s, dd, t0, st);
-                } else {
-                    if (mode == PM_START) hipLaunchKernelGGL((k_pass_batched<false, PM_START>), g, bl, 0, s, dd, t0, st);
-                    else if (mode == PM_FUSED && high) hipLaunchKernelGGL((k_pass_batched<true, PM_FUSED>), g, bl, 0, s, dd, t0, st);
-                    else if (mode == PM_FUSED) hipLaunchKernelGGL((k_pass_batched<false, PM_FUSED>), g, bl, 0, s, dd, t0, st);
-                    else if (high) hipLaunchKernelGGL((k_pass_batched<true, PM_ADD>), g, bl, 0, s, dd, t0, st);
-                    else hipLaunchKernelGGL((k_pass_batched<false, PM_ADD>), g, bl, 0, s, dd, t0, st);
-                }
-                run.launches++;
-            };
-            for (int st = 0; st <= last; ++st) {
-                const bool high = (st & 1) != 0;
-                if (st == 0) {
-                    launch(PM_START, false, 0, w.prefix[0], 0);
-                    continue;
-                }
-                // instances with K > st fuse, those with K == st finish
-                const int nfuse = (st + 1 <= last) ? w.prefix[st + 1] : 0;
-                launch(PM_FUSED, high, 0, nfuse, st);
-                launch(PM_ADD, high, nfuse, w.prefix[st] - nfuse, st);
-            }
-        }
-        if (use_graph) {
+    int graph_cached = 0;
+    float graph_ms = 0.f;
+    hipGraphExec_t exec = nullptr;
+    if (use_graph && !Ls.empty()) {
+        int dev = 0;
+        QW_HIP(hipGetDevice(&dev));
+        const std::string key = launch_key(Ls, workspace, conc ? 1 : 0);
+        std::lock_guard<std::mutex> lock(g_graph_mu);
+        for (const GraphEntry &e : g_graphs)
+            if (e.dev == dev && e.key == key) exec = e.exec;
+        if (exec) {
+            graph_cached = 1;
+        } else {
+            const auto h0 = std::chrono::steady_clock::now();
+            hipGraph_t graph = nullptr;
+            QW_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            const qw_status rs = replay(Ls, dD, ditems, dorder, (int)run.small.size(), s, side, ev[3], ev[4]);
             hipError_t e1 = hipStreamEndCapture(s, &graph);
+            if (rs != QW_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rs;
+            }
             if (e1 != hipSuccess) { set_error(std::string("graph capture: ") + hipGetErrorString(e1)); return QW_EHIP; }
             hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            if (e2 != hipSuccess) {
-                (void)hipGraphDestroy(graph);
-                set_error(std::string("graph instantiate: ") + hipGetErrorString(e2));
-                return QW_EHIP;
-            }
-            hipError_t e3 = hipGraphLaunch(exec, s);
-            hipError_t e4 = hipStreamSynchronize(s);
-            (void)hipGraphExecDestroy(exec);
             (void)hipGraphDestroy(graph);
-            if (e3 != hipSuccess || e4 != hipSuccess) {
-                set_error(std::string("graph launch: ") + hipGetErrorString(e3 != hipSuccess ? e3 : e4));
-                return QW_EHIP;
+            if (e2 != hipSuccess) { set_error(std::string("graph instantiate: ") + hipGetErrorString(e2)); return QW_EHIP; }
+            if (g_graphs.size() >= GRAPH_CACHE) {
+                (void)hipGraphExecDestroy(g_graphs.front().exec);
+                g_graphs.erase(g_graphs.begin());
             }
-        } else {
-            QW_HIP(hipGetLastError());
+            g_graphs.push_back({dev, key, exec});
+            graph_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - h0).count();
         }
+        if (timing) QW_HIP(hipEventRecord(ev[1], s));
+        QW_HIP(hipGraphLaunch(exec, s));
+    } else {
+        if (timing) QW_HIP(hipEventRecord(ev[1], s));
+        st = replay(Ls, dD, ditems, dorder, (int)run.small.size(), s, side, ev[3], ev[4]);
+        if (st != QW_OK) return st;
     }
+    run.launches = (int)Ls.size();
+    if (timing) QW_HIP(hipEventRecord(ev[2], s));
+    QW_HIP(hipStreamSynchronize(s));
     if (info) {
         info->count = count;
         info->small_count = (int)run.small.size();
@@ -626,15 +821,39 @@ static qw_status batched_impl(const qw_batch_item *items, int count, const doubl
         info->launches = run.launches;
         info->waves = (int)waves.size();
         info->amp_terms = run.amp_terms;
-        info->wave_bytes = (long long)wave_bytes;
+        info->wave_bytes = sch.wave_bytes;
+        info->onchip_nmax = sch.onchip_nmax;
+        info->concurrent = conc ? 1 : 0;
+        info->graph_cached = graph_cached;
+        info->graph_ms = graph_ms;
+        for (int c = 0; c < BC_COUNT; ++c) info->class_count[c] = run.class_count[c];
+        for (int n = 0; n <= BATCH_MAXN; ++n)
+            info->tile_class[n] = (n >= 1 && n > sch.onchip_nmax) ? (signed char)class_for(sch, n) : (signed char)-1;
     }
     if (timing) {
-        QW_HIP(hipEventRecord(ev[2], s));
-        QW_HIP(hipEventSynchronize(ev[2]));
         QW_HIP(hipEventElapsedTime(&info->setup_ms, ev[0], ev[1]));
         QW_HIP(hipEventElapsedTime(&info->loop_ms, ev[1], ev[2]));
     }
     return QW_OK;
+}
+
+static BatchSched sched_from(const qw_batch_sched *p)
+{
+    BatchSched S;
+    if (!p) return S;
+    S.wave_bytes = p->wave_bytes;
+    S.onchip_nmax = p->onchip_nmax ? p->onchip_nmax : Cfg<float>::TB;
+    S.concurrent = p->concurrent;
+    for (int n = 0; n <= BATCH_MAXN; ++n) S.cls[n] = p->tile_class[n];
+    return S;
+}
+
+static void sched_to(const BatchSched &S, qw_batch_sched *p)
+{
+    p->wave_bytes = S.wave_bytes;
+    p->onchip_nmax = S.onchip_nmax;
+    p->concurrent = S.concurrent;
+    for (int n = 0; n <= BATCH_MAXN; ++n) p->tile_class[n] = S.cls[n];
 }
 
 }  // namespace qw
@@ -649,63 +868,118 @@ size_t qw_batched_workspace_bytes_c64(const qw_batch_item *items, int count, con
     return plan_batch(items, count, hJ_pool).total;
 }
 
+static void clear_info(qw_batch_info *info)
+{
+    if (info) {
+        const int t = info->timing;
+        std::memset(info, 0, sizeof(*info));
+        info->timing = t;
+    }
+}
+
 qw_status qw_expm_action_batched_c64(const qw_batch_item *items, int count, const double *hJ_pool,
                                      const void *psi_pool, void *out_pool, qw_method method, void *workspace,
                                      size_t ws_bytes, const char *tune_cache, void *stream, qw_batch_info *info)
 {
-    if (info) {
-        const int t = info->timing;
-        std::memset(info, 0, sizeof(*info));
-        info->timing = t;
-    }
+    clear_info(info);
     if (!items || count < 1) { set_error("items and count >= 1 are required"); return QW_EINVAL; }
-    const size_t wave = read_tuned_wave(tune_cache, batch_signature(items, count));
-    return batched_impl(items, count, hJ_pool, psi_pool, out_pool, (int)method, workspace, ws_bytes, wave, true,
+    BatchSched S;
+    (void)read_tuned_sched(tune_cache, batch_signature(items, count), &S);
+    return batched_impl(items, count, hJ_pool, psi_pool, out_pool, (int)method, workspace, ws_bytes, S, true,
                         reinterpret_cast<hipStream_t>(stream), info);
-}
-
-qw_status qw_batched_tune_c64(const qw_batch_item *items, int count, const double *hJ_pool, const void *psi_pool,
-                              void *out_pool, void *workspace, size_t ws_bytes, const char *tune_cache,
-                              void *stream, long long *best_wave_bytes)
-{
-    if (!items || count < 1) { set_error("items and count >= 1 are required"); return QW_EINVAL; }
-    const long long cands[] = {0, 512ll << 20, 256ll << 20, 192ll << 20, 128ll << 20, 64ll << 20};
-    float best_ms = INFINITY;
-    long long best = 0;
-    for (long long w : cands) {
-        qw_batch_info bi{};
-        bi.timing = 1;
-        qw_status st = batched_impl(items, count, hJ_pool, psi_pool, out_pool, QW_CHEB, workspace, ws_bytes,
-                                    (size_t)w, true, reinterpret_cast<hipStream_t>(stream), &bi);
-        if (st != QW_OK) return st;
-        if (bi.loop_ms < best_ms) {
-            best_ms = bi.loop_ms;
-            best = w;
-        }
-    }
-    if (best_wave_bytes) *best_wave_bytes = best;
-    if (tune_cache) {
-        FILE *f = std::fopen(tune_cache, "a");
-        if (!f) { set_error(std::string("cannot write tune cache ") + tune_cache); return QW_EINVAL; }
-        std::fprintf(f, "%s %lld %.3f\n", batch_signature(items, count).c_str(), best, best_ms);
-        std::fclose(f);
-    }
-    return QW_OK;
 }
 
 qw_status qw_expm_action_batched_c64_sched(const qw_batch_item *items, int count, const double *hJ_pool,
                                            const void *psi_pool, void *out_pool, qw_method method,
-                                           void *workspace, size_t ws_bytes, long long wave_bytes, int use_graph,
-                                           void *stream, qw_batch_info *info)
+                                           void *workspace, size_t ws_bytes, const qw_batch_sched *sched,
+                                           int use_graph, void *stream, qw_batch_info *info)
 {
-    if (info) {
-        const int t = info->timing;
-        std::memset(info, 0, sizeof(*info));
-        info->timing = t;
+    clear_info(info);
+    return batched_impl(items, count, hJ_pool, psi_pool, out_pool, (int)method, workspace, ws_bytes, sched_from(sched),
+                        use_graph != 0, reinterpret_cast<hipStream_t>(stream), info);
+}
+
+// Coordinate search over the schedule, each candidate timed on one call with
+// its graph built beforehand (HIP events around the passes only): the tile
+// class of each size bucket in turn, then the one-workgroup limit, running the
+// one-workgroup launch beside the passes, and the wave size.
+qw_status qw_batched_tune_c64(const qw_batch_item *items, int count, const double *hJ_pool, const void *psi_pool,
+                              void *out_pool, void *workspace, size_t ws_bytes, const char *tune_cache,
+                              void *stream, qw_batch_sched *best_out)
+{
+    if (!items || count < 1) { set_error("items and count >= 1 are required"); return QW_EINVAL; }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    auto time_of = [&](const BatchSched &S, float *ms) -> qw_status {
+        qw_batch_info bi{};
+        qw_status st = batched_impl(items, count, hJ_pool, psi_pool, out_pool, QW_CHEB, workspace, ws_bytes, S, true,
+                                    s, &bi);   // builds (or finds) the graph
+        if (st != QW_OK) return st;
+        bi = qw_batch_info{};
+        bi.timing = 1;
+        st = batched_impl(items, count, hJ_pool, psi_pool, out_pool, QW_CHEB, workspace, ws_bytes, S, true, s, &bi);
+        *ms = bi.loop_ms;
+        return st;
+    };
+    int present[BATCH_MAXN + 1] = {0};
+    for (int i = 0; i < count; ++i) present[items[i].n] = 1;
+    BatchSched best;
+    float best_ms = 0.f;
+    qw_status st = time_of(best, &best_ms);
+    if (st != QW_OK) return st;
+    auto consider = [&](const BatchSched &S) -> qw_status {
+        if (validate_sched(S) != QW_OK) return QW_OK;   // not a valid candidate for these sizes
+        float ms = 0.f;
+        const qw_status st2 = time_of(S, &ms);
+        if (st2 != QW_OK) return st2;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = S;
+        }
+        return QW_OK;
+    };
+    const int buckets[][2] = {{13, 16}, {17, 18}, {19, 20}, {21, 22}};
+    for (const auto &bk : buckets) {
+        bool any = false;
+        for (int n = bk[0]; n <= bk[1]; ++n) any = any || present[n];
+        if (!any) continue;
+        for (int c = 0; c < BC_COUNT; ++c) {
+            BatchSched S = best;
+            for (int n = bk[0]; n <= bk[1]; ++n) S.cls[n] = (signed char)c;
+            bool same = true;
+            for (int n = bk[0]; n <= bk[1]; ++n)
+                if (present[n] && n > S.onchip_nmax && class_for(S, n) != class_for(best, n)) same = false;
+            if (same) continue;
+            st = consider(S);
+            if (st != QW_OK) return st;
+        }
     }
-    if (wave_bytes < 0) { set_error("wave_bytes must be >= 0"); return QW_EINVAL; }
-    return batched_impl(items, count, hJ_pool, psi_pool, out_pool, (int)method, workspace, ws_bytes,
-                        (size_t)wave_bytes, use_graph != 0, reinterpret_cast<hipStream_t>(stream), info);
+    if (present[13]) {
+        BatchSched S = best;
+        S.onchip_nmax = (best.onchip_nmax == 13) ? 12 : 13;
+        if (S.onchip_nmax == 12) S.cls[13] = BC_NARROW;
+        st = consider(S);
+        if (st != QW_OK) return st;
+    }
+    {
+        BatchSched S = best;
+        S.concurrent = !best.concurrent;
+        st = consider(S);
+        if (st != QW_OK) return st;
+    }
+    for (long long w : {512ll << 20, 256ll << 20, 128ll << 20}) {
+        BatchSched S = best;
+        S.wave_bytes = w;
+        st = consider(S);
+        if (st != QW_OK) return st;
+    }
+    if (best_out) sched_to(best, best_out);
+    if (tune_cache) {
+        FILE *f = std::fopen(tune_cache, "a");
+        if (!f) { set_error(std::string("cannot write tune cache ") + tune_cache); return QW_EINVAL; }
+        std::fprintf(f, "%s %s ms=%.3f\n", batch_signature(items, count).c_str(), sched_fields(best).c_str(), best_ms);
+        std::fclose(f);
+    }
+    return QW_OK;
 }
 
 }  // extern "C"

@@ -184,3 +184,31 @@ def test_library_cf_against_remez(oracle_mod, a, tol):
     assert ec <= Ec * 1.001 + 1e-15 and es <= Es * 1.001 + 1e-15
     assert abs(bound / (Ec + Es) - 1) < 1e-3
     assert bound <= tol
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct of include/qwexp.h has the size and field offsets the
+    ctypes binding assumes (compiled with the host C compiler)."""
+    import ctypes
+    import subprocess
+    import paper_2608_12058_amd as qw
+    pairs = {"qw_info": qw.QwInfo, "qw_cfet_info": qw.CfetInfo, "qw_batch_item": qw.BatchItem,
+             "qw_batch_info": qw.BatchInfo, "qw_batch_sched": qw.BatchSched, "qw_grad_info": qw.GradInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "qwexp.h"', "int main(void) {"]
+    for cname, cls in pairs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            if field == "reserved":
+                continue
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = str(tmp_path / "layout")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.check_call(["gcc", "-I", os.path.join(root, "include"), str(src), "-o", exe])
+    for line in subprocess.check_output([exe]).decode().splitlines():
+        cname, field, val = line.split()
+        cls = pairs[cname]
+        got = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(val), (cname, field, got, val)

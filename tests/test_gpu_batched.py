@@ -73,8 +73,11 @@ def test_batched_vs_oracle_and_single(env, oracle_mod):
         assert np.max(np.abs(single - got)) <= 1e-6, (i, n)
 
 
-@pytest.mark.parametrize("wave,graph", [(0, False), (64 << 20, True), (1 << 20, True), (1 << 20, False)])
-def test_schedules_agree(env, wave, graph):
+@pytest.mark.parametrize("wave,graph,conc", [(0, False, False), (64 << 20, True, False), (1 << 20, True, False),
+                                             (1 << 20, False, False), (0, True, True), (1 << 20, False, True)])
+def test_schedules_agree(env, wave, graph, conc):
+    """Waves, graph or eager launches and the one-workgroup launch on a side
+    stream change only the order of independent work: bit-identical outputs."""
     torch, qw = env
     insts = mixed_instances()
     b = qw.Batch(insts)
@@ -84,16 +87,75 @@ def test_schedules_agree(env, wave, graph):
         qw.expm_action_batched(b, stream=stream)
         ref = b.out_pool.clone()
         b.out_pool.zero_()
-        info = qw.expm_action_batched(b, stream=stream, wave_bytes=wave, use_graph=graph)
+        info = qw.expm_action_batched(b, stream=stream, sched=dict(wave_bytes=wave, concurrent=conc),
+                                      use_graph=graph)
     stream.synchronize()
     if wave == (1 << 20):
         assert info["waves"] > 1
+    assert info["concurrent"] == int(conc)
     assert torch.equal(ref, b.out_pool)
 
 
+@pytest.mark.parametrize("classes,onchip", [({n: 1 for n in range(14, 21)}, 13),
+                                            ({n: 2 for n in range(14, 23)}, 13),
+                                            ({13: 1, 14: 1, 15: 1, 16: 1, 21: 2, 22: 2}, 12)])
+def test_tile_classes_vs_oracle(env, oracle_mod, classes, onchip):
+    """Other tile classes (2^12 tiles for n <= 20, 2^13 tiles with 512 threads)
+    and 13-qubit instances in the multi-pass path: every instance against the
+    oracle (1e-5) and the default schedule (float rounding)."""
+    torch, qw = env
+    insts = mixed_instances()
+    b = qw.Batch(insts)
+    fill_states(torch, b, insts)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        qw.expm_action_batched(b, stream=stream)
+        ref = b.out_pool.clone()
+        info = qw.expm_action_batched(b, stream=stream, sched=dict(onchip_nmax=onchip, tile_class=classes))
+    stream.synchronize()
+    for n, c in classes.items():
+        if n > onchip and any(ins["n"] == n for ins in insts):
+            assert info["tile_class"][n] == c
+    assert info["onchip_nmax"] == onchip
+    assert torch.max(torch.abs(ref - b.out_pool)).item() <= 1e-6
+    for i, ins in enumerate(insts):
+        n = ins["n"]
+        E = oracle_mod.energies(n, ins["h"], ins["J"])
+        want = oracle_mod.expm_action(n, E, ins["gamma"], ins["t"], b.state(i).cpu().numpy().astype(np.complex128),
+                                      1e-13)
+        assert rel(b.output(i).cpu().numpy().astype(np.complex128), want) <= 1e-5, (i, n)
+
+
+def test_invalid_tile_class_is_refused(env):
+    torch, qw = env
+    insts = mixed_instances()
+    b = qw.Batch(insts)
+    with pytest.raises(qw.QwError):
+        qw.expm_action_batched(b, sched=dict(tile_class={22: 1}))   # 2^12 tiles cannot hold 22 qubits
+
+
+def test_graph_is_reused(env):
+    """A second call with the same launch sequence replays the instantiated
+    graph (no capture) and gives the same output."""
+    torch, qw = env
+    insts = mixed_instances()
+    b = qw.Batch(insts)
+    fill_states(torch, b, insts)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        i1 = qw.expm_action_batched(b, stream=stream, sched=dict(wave_bytes=32 << 20))
+        o1 = b.out_pool.clone()
+        b.out_pool.zero_()
+        i2 = qw.expm_action_batched(b, stream=stream, sched=dict(wave_bytes=32 << 20), timing=1)
+    stream.synchronize()
+    assert i1["graph_cached"] == 0 and i1["graph_ms"] > 0
+    assert i2["graph_cached"] == 1 and i2["graph_ms"] == 0
+    assert torch.equal(o1, b.out_pool)
+
+
 def test_repeated_calls_with_work_between(env):
-    """The graph is rebuilt and replayed on every call; eager torch work and
-    synchronisations in between must not change any result."""
+    """The first call captures the graph and the later ones replay it; eager
+    torch work and synchronisations in between must not change any result."""
     torch, qw = env
     insts = mixed_instances()
     b = qw.Batch(insts)
@@ -138,8 +200,13 @@ def test_tune_cache_roundtrip(env, tmp_path):
         best = qw.batched_tune(b, cache, stream=stream)
         info = qw.expm_action_batched(b, tune_cache=cache, stream=stream)
     stream.synchronize()
-    assert info["wave_bytes"] == best
-    assert open(cache).read().split()[1] == str(best)
+    assert info["wave_bytes"] == best["wave_bytes"]
+    assert info["onchip_nmax"] == best["onchip_nmax"] and info["concurrent"] == best["concurrent"]
+    for n, c in best["tile_class"].items():
+        if n > best["onchip_nmax"] and n in info["tile_class"]:
+            assert info["tile_class"][n] == c
+    fields = dict(f.split("=") for f in open(cache).read().split()[1:])
+    assert int(fields["wave"]) == best["wave_bytes"] and int(fields["onchip"]) == best["onchip_nmax"]
 
 
 def test_config3_batched_256(env, oracle_mod):
