@@ -381,8 +381,11 @@ size_t qw_anneal_workspace_bytes_c64(int n, const double *h, const double *J, in
  *   h, J       : host couplings (SK layout as above); gamma, t: host, S values.
  *   psi0       : device complex64 initial state (2^n amplitudes).
  *   ckpt_every : window of the b_k recomputation; b_k pairs are checkpointed
- *                every ckpt_every terms during the forward sweep (<= 0: one
- *                window per segment, no checkpoints).
+ *                every ckpt_every terms during the forward sweep (0: one
+ *                window per segment, no checkpoints); < 0: every b_k of every
+ *                segment is kept (sum_s K_s vectors of workspace) and the
+ *                backward sweep recomputes nothing.  The results are
+ *                bit-identical for every ckpt_every.
  *   E, dgamma (S), dt (S), dh (n), dJ (n(n-1)/2): host outputs.
  *   psiT_out   : device complex64, receives psi_S (may be NULL).
  * 1 <= n <= 28.  Synchronises the stream once per segment. */

@@ -382,11 +382,13 @@ struct SegPlan {
     int K, C, W;
     std::vector<double> alpha, dalpha;   // coefficients and d alpha / d a
     std::vector<int> slot;               // checkpoint slot of b_j (j = 0..K+1), -1 if none
+    size_t sbase = 0;                    // store mode: window slot of b_1
 };
 
 struct GradLayout {
     size_t states, erel, A, B, vbar, G, win, ckpt, part, partm, walsh, wres, hj, q, red, mpart, total;
     int nwin, nckpt, ntiles_lo, npar;
+    bool store;   // every b_k of every segment kept (win holds them all, no recomputation)
 };
 
 // Launch helpers over the tile shapes the forward path chooses (tile_cfg_for).
@@ -443,7 +445,13 @@ static GradLayout grad_layout(int n, int S, const int *Kb, int ckpt_every)
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
     L.nwin = 1;
     L.nckpt = 0;
-    for (int s = 0; s < S; ++s) {
+    L.store = ckpt_every < 0;
+    if (L.store) {
+        // b_1 .. b_K of segment s at slots sum_{s' < s} max(Kb[s'], 1) + j - 1
+        L.nwin = 0;
+        for (int s = 0; s < S; ++s) L.nwin += std::max(Kb[s], 1);
+    }
+    for (int s = 0; s < S && !L.store; ++s) {
         const int K = std::max(Kb[s], 1);
         const int C = grad_window(ckpt_every, K);
         const int W = (K + C - 1) / C;
@@ -569,6 +577,7 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
     const int P = (int)plan.size();
     std::vector<SegPlan> seg(S);
     int ck_next = 0;
+    size_t store_next = 0;
     for (int q = 0; q < S; ++q) {
         SegPlan &sp = seg[q];
         double r = half + n * std::fabs(gamma[q]);
@@ -595,9 +604,11 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
         for (int k = 0; k <= sp.K; ++k)
             sp.dalpha[k] = (k == 0) ? -Jm[1] : (Jm[k - 1] - Jm[k + 1]);
         const int K = std::max(sp.K, 1);
-        sp.C = grad_window(ckpt_every, K);
+        sp.C = L.store ? K : grad_window(ckpt_every, K);
         sp.W = (sp.K == 0) ? 0 : (sp.K + sp.C - 1) / sp.C;
         sp.slot.assign(sp.K + 3, -1);
+        sp.sbase = store_next;
+        store_next += (size_t)std::max(Kb[q], 1);
         for (int w = 0; w + 1 < sp.W; ++w) {
             const int Tw = (w + 1) * sp.C;
             for (int j = Tw + 1; j <= std::min(Tw + 2, sp.K); ++j)
@@ -650,6 +661,38 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
             const double pr = cr * sp.ph_r - ci * sp.ph_i, pi = cr * sp.ph_i + ci * sp.ph_r;
             hipLaunchKernelGGL(k_scale<float>, dim3(eg_grid), dim3(256), 0, s, reinterpret_cast<const CVec<float> *>(v),
                                reinterpret_cast<CVec<float> *>(y), (float)pr, (float)pi, (uint64_t)(N / 2));
+            continue;
+        }
+        if (L.store) {
+            // every b_j goes to its own slot Wst(j); the partial sums live in B.
+            // Same passes and arithmetic as below, so the b_j are bit-identical.
+            auto Wst = [&](int j) { return vec(L.win, sp.sbase + (size_t)(j - 1)); };
+            C *Y = vec(L.B, 0);
+            coef_of(sp.alpha, sp.K, cr, ci);
+            hipLaunchKernelGGL(k_scale<float>, dim3(eg_grid), dim3(256), 0, s,
+                               reinterpret_cast<const CVec<float> *>(v), reinterpret_cast<CVec<float> *>(Wst(sp.K)),
+                               (float)cr, (float)ci, (uint64_t)(N / 2));
+            auto scale_of = [](int k) { return k == 0 ? 1.0 : 2.0; };
+            for (const SchedPass &ps : fused_schedule(sp.K, P)) {
+                const float pr = ps.fin ? sp.ph_r : 1.f, pi = ps.fin ? sp.ph_i : 0.f;
+                const C *b1 = Wst(ps.k + 1);
+                if (ps.mode == PM_START) {
+                    coef_of(sp.alpha, ps.k, cr, ci);
+                    const C *acc = (ps.k + 2 <= sp.K) ? (P == 1 ? Wst(ps.k + 2) : nullptr) : nullptr;
+                    if (P > 1 && ps.k != sp.K - 1) { set_error("internal: start pass inside a term"); return QW_EINVAL; }
+                    C *dst = ps.fin ? y : (P == 1 ? Wst(ps.k) : Y);
+                    launch_clenshaw_pass(PM_START, ps.orient, b1, acc, dst, nullptr, cr, ci, scale_of(ps.k), 0.0, pr, pi,
+                                         sp, v);
+                } else if (ps.mode == PM_ADD) {
+                    launch_clenshaw_pass(PM_ADD, ps.orient, b1, Y, ps.fin ? y : Y, nullptr, 0.0, 0.0, scale_of(ps.k),
+                                         0.0, pr, pi, sp, v);
+                } else {
+                    coef_of(sp.alpha, ps.k - 1, cr, ci);
+                    launch_clenshaw_pass(PM_FUSED, ps.orient, b1, Y, Wst(ps.k), Y, cr, ci, scale_of(ps.k),
+                                         scale_of(ps.k - 1), 1.f, 0.f, sp, v);
+                }
+            }
+            QW_HIP(hipGetLastError());
             continue;
         }
         // fused schedule in two ping-pong buffers; X holds the last completed b_k
@@ -735,12 +778,15 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
         const C *prevp = nullptr;
         for (int w = 0; w < sp.W; ++w) {
             const int Bw = w * sp.C + 1, Tw = std::min((w + 1) * sp.C, sp.K);
-            C *win = vec(L.win, 0);
+            // store mode: one window, b_1 .. b_K already in their slots
+            C *win = L.store ? vec(L.win, sp.sbase) : vec(L.win, 0);
             // recompute b_Tw .. b_Bw into win[j - Bw]
-            const C *x1, *x2;
-            int jstart;
+            const C *x1 = nullptr, *x2 = nullptr;
+            int jstart = 0;
             double cr, ci;
-            if (Tw == sp.K) {
+            if (L.store) {
+                // nothing to recompute
+            } else if (Tw == sp.K) {
                 coef_of(sp.alpha, sp.K, cr, ci);
                 hipLaunchKernelGGL(k_scale<float>, dim3(eg_grid), dim3(256), 0, s,
                                    reinterpret_cast<const CVec<float> *>(v),
@@ -758,7 +804,7 @@ static qw_status grad_impl(int n, const double *h, const double *J, int S, const
             // every term visits the orientations in the order the forward sweep
             // used (mirrored when the window starts on the other parity), so the
             // recomputed b_j equal the forward ones bit for bit
-            {
+            if (!L.store) {
                 auto Wj = [&](int j) { return win + (size_t)(j - Bw) * N; };
                 auto Bj = [&](int j) -> const C * {
                     if (j <= jstart) return Wj(j);

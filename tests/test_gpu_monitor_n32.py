@@ -173,8 +173,39 @@ def test_n32_c64_on_the_fly_matches_c128_stored(env):
     nrm = torch.linalg.vector_norm(y).item()
     del y, x
     torch.cuda.empty_cache()
-    # 2^14-amplitude complex64 tiles: 14 + 9 + 9 bits; 2^12-amplitude complex128
-    # tiles: 12 + 9 + 9 + 2 bits
+    # complex64: three orientations (10 + 13 + 9 bits, the contiguous one in the
+    # middle); 2^12-amplitude complex128 tiles: 12 + 9 + 9 + 2 bits
     assert i64["passes"] == 3 and i128["passes"] == 4
     assert abs(nrm - 1.0) < 1e-11
     assert rel(got64, got128) <= 1e-5
+
+
+def test_config5_n32_t5_c64_matches_c128(env):
+    """The 32-qubit workload the benchmark times (SK seed 0, gamma = 1, t = 5,
+    tol 2^-23, |+>, diagonal rebuilt per tile, output over the input) against
+    the complex128 path (stored double diagonal, tol 1e-12) on 4096 sampled
+    amplitudes, run one after the other (the complex128 call alone holds 240
+    GB); both norms stay 1."""
+    torch, qw = env
+    h, J = synth.sk_instance(N32, 0)
+    rng = np.random.default_rng(32)
+    idx = np.concatenate([[0, 1, (1 << N32) - 1], rng.integers(0, 1 << N32, 4093)])
+    tidx = torch.as_tensor(idx, device="cuda")
+    x = synth.plus_state_torch(N32, "cuda", torch.complex64)
+    y, i64 = qw.expm_action(x, 1.0, 5.0, h=h, J=J, tol=2.0 ** -23, out=x)
+    got64 = y[tidx].cpu().numpy().astype(np.complex128)
+    n64 = torch.linalg.vector_norm(y.to(torch.complex128)).item()
+    del y, x
+    torch.cuda.empty_cache()
+    x = synth.plus_state_torch(N32, "cuda", torch.complex128)
+    y, i128 = qw.expm_action(x, 1.0, 5.0, h=h, J=J, tol=1e-12, out=x)
+    got128 = y[tidx].cpu().numpy()
+    n128 = torch.linalg.vector_norm(y).item()
+    del y, x
+    torch.cuda.empty_cache()
+    err = rel(got64, got128)
+    print(f"config 5: K {i64['K']} (c128 {i128['K']}), sampled rel err {err:.2e}, norms {n64:.9f} / {n128:.12f}",
+          flush=True)
+    assert i64["otf_mask"] == 0b101 and i64["passes"] == 3
+    assert abs(n64 - 1.0) < 1e-5 and abs(n128 - 1.0) < 1e-11
+    assert err <= 1e-5
