@@ -877,7 +877,7 @@ qw_status qw_expm_action_c64_noalloc(int n, const float *diag, const double *h, 
 
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.11 (gfx950, fused passes, per-orientation launch plans, contiguous middle orientation, diagonal rebuilt in the end orientations)"; }
+const char *qw_version(void) { return "qwexp 0.12 (gfx950, fused passes, per-orientation launch plans, contiguous middle orientation, diagonal rebuilt in the end orientations, flips of a thread's own vectors from registers)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {

@@ -460,16 +460,26 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     }
     __syncthreads();
 
-    // Flip sums of the VE consecutive elements e..e+VE-1 (e a multiple of VE).
-    // A flip of tile bit >= log2(VE) maps the group onto another aligned group,
-    // read from LDS as one 16-byte vector; a flip of bit 0 (complex64 only)
-    // swaps the two elements of the group, which this thread holds in `self`.
-    auto flips = [&](uint32_t e, const V &self, R (&sr)[VE], R (&si)[VE]) {
+    // Flip sums of the VE consecutive elements e..e+VE-1 of vector q (e a multiple
+    // of VE), whose values are arr[q].  Tile element bits split into the vector's
+    // own element (bit 0 with VE = 2), the thread (bits up to LOG_NV - 1) and the
+    // vector index q (bits LOG_NV and up).  A flipped thread bit maps the group
+    // onto another thread's aligned group, read from LDS as one 16-byte vector; a
+    // flipped q bit onto another vector of the same thread, already in its
+    // registers (arr[q ^ 2^b]: no LDS read); a flip of bit 0 swaps the two
+    // elements of arr[q].  The flips are summed in increasing bit order.
+    constexpr int LOG_NV = (NT * VE >= 2048) ? 11 : (NT * VE >= 1024) ? 10 : (NT * VE >= 512) ? 9 : 8;
+    static_assert((1 << LOG_NV) == NT * VE, "power-of-two vectors per slice");
+    constexpr int QB = (PER >= 16) ? 4 : (PER >= 8) ? 3 : (PER >= 4) ? 2 : (PER >= 2) ? 1 : 0;
+    static_assert((1 << QB) == PER, "power-of-two vectors per thread");
+    const int j_lds = max(0, min(a.h, LOG_NV - a.L));   // group bits below the q bits
+    auto flips = [&](int q, uint32_t e, const V (&arr)[PER], R (&sr)[VE], R (&si)[VE]) {
 #pragma unroll
         for (int v = 0; v < VE; ++v) {
             sr[v] = R(0);
             si[v] = R(0);
         }
+        const V &self = arr[q];
         const V *lv = reinterpret_cast<const V *>(lds);
         auto step = [&](int j) {
             const uint32_t m = 1u << (a.L + j);
@@ -490,9 +500,20 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
         if constexpr (VE == 2) {
             // kept rolled: unrolling a known h hoists every LDS read and spills
 #pragma unroll 1
-            for (int j = 0; j < a.h; ++j) step(j);
+            for (int j = 0; j < j_lds; ++j) step(j);
         } else {
-            for (int j = 0; j < a.h; ++j) step(j);
+            for (int j = 0; j < j_lds; ++j) step(j);
+        }
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            if (LOG_NV + b >= a.L && LOG_NV + b < a.L + a.h) {
+                const V &nb = arr[q ^ (1 << b)];
+#pragma unroll
+                for (int v = 0; v < VE; ++v) {
+                    sr[v] += nb.v[v].x;
+                    si[v] += nb.v[v].y;
+                }
+            }
         }
     };
     // Diagonal of element (q, v) (global index idx) for START: loaded from d
@@ -560,7 +581,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
             const uint32_t e = (uint32_t)(q * NT + threadIdx.x) * VE;
             if (e < TE) {
                 R sr[VE], si[VE];
-                flips(e, own[q], sr, si);
+                flips(q, e, own, sr, si);
                 const R sg = a.scale * a.g;
 #pragma unroll
                 for (int v = 0; v < VE; ++v) {
@@ -589,7 +610,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                 R sr[VE], si[VE];
                 V psl;   // one 16-byte load, hinted as the pass
                 if constexpr (!EARLY_PSI) psl = ld_v<R, PD_HINT>(a.psi + idx);
-                flips(e, accv[q], sr, si);
+                flips(q, e, accv, sr, si);
 #pragma unroll
                 for (int v = 0; v < VE; ++v) {
                     R dd;
@@ -612,7 +633,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
                 const uint64_t idx = tile_index(base, e, a.L, a.g0);
                 V out;
                 R sr_[VE], si_[VE];
-                flips(e, own[q], sr_, si_);
+                flips(q, e, own, sr_, si_);
 #pragma unroll
                 for (int v = 0; v < VE; ++v) {
                     const R sr = sr_[v], si = si_[v];

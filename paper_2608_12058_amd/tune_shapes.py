@@ -11,8 +11,16 @@ caller buffers) and prints two tables:
          the kernels have, ranked by the time of one term of the fused
          schedule: the ADD pass of the middle orientation plus half of each end
          orientation's fused pass.
+  g0     (--g0-sweep) one group of 8 flipped bits moved up the index, g0 = L ..
+         n - 8, in the two shapes the 28-qubit plan uses (2^13 tiles with 512
+         threads and 256-byte rows, 2^14 tiles with 1024 threads and 512-byte
+         rows), ADD and on-the-fly FUSED: how the rate of a strided pass
+         depends on how far apart its rows lie (the rows of one tile fall in
+         2^(number of group bits >= 18) different 2 MB blocks of a complex64
+         vector).
 
     python -m paper_2608_12058_amd.tune_shapes --n 28 [--no-rows] [--reps 6]
+    python -m paper_2608_12058_amd.tune_shapes --n 28 --g0-sweep [--g0 12,16,20] [--reps 1]
 """
 from __future__ import annotations
 
@@ -33,6 +41,8 @@ def main():
     ap.add_argument("--no-rows", action="store_true")
     ap.add_argument("--no-plans", action="store_true")
     ap.add_argument("--stored-diag", action="store_true", help="also time fused passes that read a stored diagonal")
+    ap.add_argument("--g0-sweep", action="store_true", help="only the table of one 8-bit group at every offset g0")
+    ap.add_argument("--g0", default="", help="comma-separated offsets for --g0-sweep (default: all)")
     args = ap.parse_args()
     import torch
     import paper_2608_12058_amd as qw
@@ -64,6 +74,24 @@ def main():
         return e0.elapsed_time(e1) / args.reps * 1e3
 
     print(f"# pass-shape sweep, n = {n} (complex64, streaming loads and stores), microseconds per pass\n")
+    if args.g0_sweep:
+        # (mode, tile bits, threads, on the fly, passenger bits L, bytes per amplitude)
+        kinds = ((ADD, 13, 512, 0, 5, 24), (ADD, 14, 1024, 0, 6, 24), (FUSED, 13, 512, 1, 5, 40),
+                 (FUSED, 14, 1024, 1, 6, 40))
+        want = [int(x) for x in args.g0.split(",") if x.strip()]
+        print("| pass | tile | threads | L | g0 | 2 MB blocks per tile | tile order | us | TB/s moved |")
+        print("|---|---|---|---|---|---|---|---|---|")
+        for mode, tb, nt, otf, L, bpa in kinds:
+            h = tb - L
+            for g0 in range(L, n - h + 1):
+                if want and g0 not in want:
+                    continue
+                for xcd in (0, 1):
+                    us = timed(mode, tb, nt, otf, L, g0, h, xcd)
+                    blocks = 1 << max(0, g0 + h - max(g0, 18))   # group bits at or above bit 18
+                    print(f"| {'add' if mode == ADD else 'fused rebuilt'} | 2^{tb} | {nt} | {L} | {g0} | {blocks} | "
+                          f"{'XCD-major' if xcd else 'launch'} | {us:.1f} | {bpa * N / us / 1e6:.2f} |", flush=True)
+        return
     if not args.no_rows:
         print("| tile | threads | L | row bytes | flipped bits | us | TB/s at 24 B/amp |\n|---|---|---|---|---|---|---|")
         for tb, nt in ((12, 1024), (13, 1024), (14, 1024)):
