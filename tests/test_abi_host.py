@@ -69,7 +69,8 @@ def test_degree_pin_151():
     assert abs(len(al) - 151) <= 1
 
 
-@pytest.mark.parametrize("a,tol", [(22.07, 1e-12), (120.0, 2.0 ** -23), (470.2, 2.0 ** -23), (47.0, 1e-6)])
+@pytest.mark.parametrize("a,tol", [(22.07, 1e-12), (120.0, 2.0 ** -23), (470.2, 2.0 ** -23), (47.0, 1e-6),
+                                   (1000.0, 2.0 ** -23), (2000.0, 1e-10)])
 def test_cf_coefficients_match_oracle_and_tolerance(oracle_mod, a, tol):
     al, lam = qw.cheb_coeffs(a, tol, "cf")
     ref, lam_ref = oracle_mod.cf_coeffs(a, tol)
