@@ -324,7 +324,8 @@ size_t qw_batched_workspace_bytes_c64(const qw_batch_item *items, int count, con
  * persistent on-chip launch; larger ones in grouped two-pass launches (one per
  * tile class and step) captured into a HIP graph (eager launches when stream
  * is NULL), which later calls with the same launch sequence and workspace
- * replay without capturing again (a few graphs are kept per process).  The
+ * replay without capturing again (four graphs are kept per process; a call
+ * that evicts the oldest waits for its device to finish all work first).  The
  * schedule comes from the tune file tune_cache (may be NULL: the default).
  *   items : host array of count items; hJ_pool: host doubles;
  *   psi_pool / out_pool : device complex64 pools (16-byte aligned; output

@@ -492,7 +492,8 @@ static qw_status replay(const std::vector<BLaunch> &Ls, const BatchDesc *dD, con
 // Instantiated graphs of recent calls, keyed by the device, the workspace and
 // the exact launch sequence (which fixes every kernel argument: descriptors
 // and tile tables are re-uploaded into the same workspace places before each
-// replay).  At most GRAPH_CACHE entries; the oldest is destroyed first.
+// replay).  At most GRAPH_CACHE entries; the oldest is destroyed first, after
+// its device has finished its work (an eviction waits for the whole device).
 static constexpr size_t GRAPH_CACHE = 4;
 struct GraphEntry {
     int dev;
@@ -797,8 +798,16 @@ static qw_status batched_impl(const qw_batch_item *items, int count, const doubl
             (void)hipGraphDestroy(graph);
             if (e2 != hipSuccess) { set_error(std::string("graph instantiate: ") + hipGetErrorString(e2)); return QW_EHIP; }
             if (g_graphs.size() >= GRAPH_CACHE) {
-                (void)hipGraphExecDestroy(g_graphs.front().exec);
+                // The oldest graph may still run on a stream of an earlier call
+                // (the lock covers lookups and launches, not their execution):
+                // its device finishes all work before the graph is destroyed.
+                const GraphEntry old = g_graphs.front();
                 g_graphs.erase(g_graphs.begin());
+                if (old.dev != dev) QW_HIP(hipSetDevice(old.dev));
+                const hipError_t es = hipDeviceSynchronize();
+                if (old.dev != dev) QW_HIP(hipSetDevice(dev));
+                QW_HIP(es);
+                (void)hipGraphExecDestroy(old.exec);
             }
             g_graphs.push_back({dev, key, exec});
             graph_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - h0).count();
