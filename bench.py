@@ -372,8 +372,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
-              "the hot path here is the single-GPU kernel; multi-GPU sharding is described in DESIGN.md "
-              "but not built.", file=sys.stderr)
+              "the hot path here is the single-GPU kernel; sharding one instance over several GPUs "
+              "is not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
