@@ -195,7 +195,8 @@ size_t qw_workspace_bytes(int n, int precision, int on_the_fly);
  *   diag : device, N = 2^n energies (float for _f32, double for _f64), or NULL
  *          to compute E(z) = sum_{j<k} J_jk s_j s_k + sum_j h_j s_j on device
  *          from h (host, n doubles) and J (host, packed row-major upper
- *          triangle, n(n-1)/2 doubles).
+ *          triangle, n(n-1)/2 doubles).  A NaN or infinite energy gives
+ *          QW_EINVAL.
  *   workspace : device, >= qw_workspace_bytes(n, 64|128, 0) bytes.
  * Synchronises the stream (16-byte read-back). */
 qw_status qw_spectral_bound_f32(int n, const float *diag, const double *h, const double *J,
@@ -212,8 +213,9 @@ qw_status qw_spectral_bound_f64(int n, const double *diag, const double *h, cons
  *             generate them from h, J (host arrays as in qw_spectral_bound_*).
  *             With diag == NULL and n >= 31 the complex64 call recomputes the
  *             diagonal inside every Clenshaw term from per-tile tables and never
- *             stores it (from 26 to 28 qubits only the pass of the top qubits
- *             does, the others read the stored one); complex128 stores it in the
+ *             stores it (from 26 to 28 qubits the fused passes of the two high
+ *             bit groups rebuild it and no pass reads a stored one, although
+ *             the workspace still has room for it); complex128 stores it in the
  *             workspace (n = 32: the workspace is 172 GB, with psi 240 GB in
  *             all).  A recomputed value is summed in double and rounded once.
  *   psi_in  : device, N complex values; psi_out: device, N complex values; they

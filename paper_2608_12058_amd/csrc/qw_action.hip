@@ -49,6 +49,10 @@ __global__ void __launch_bounds__(256) k_minmax_diag(const R *d, uint64_t N, dou
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const double v = (double)d[i];
+        if (v != v) {   // NaN: fmin / fmax would drop it; make the range non-finite instead
+            mn = -INFINITY;
+            mx = INFINITY;
+        }
         mn = fmin(mn, v);
         mx = fmax(mx, v);
     }

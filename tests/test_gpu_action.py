@@ -193,6 +193,20 @@ def test_degenerate_cases(env, prec):
     assert rel(y, np.exp(-1j * 3.0 * 0.37) * psi) <= (1e-6 if prec == 64 else 1e-14)
 
 
+@pytest.mark.parametrize("prec", [64, 128])
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_non_finite_diagonal_is_rejected(env, prec, bad):
+    """A caller diagonal with one NaN or infinite energy (n = 16, on the
+    multi-pass path) is refused with QW_EINVAL before any pass runs."""
+    torch, qw = env
+    n = 16
+    E = np.linspace(-1.0, 1.0, 1 << n)
+    E[12345] = bad
+    with pytest.raises(qw.QwError) as ei:
+        _run(env, n, synth.plus_state(n), 1.0, 1.0, 1e-8, prec, diag_np=E)
+    assert ei.value.status == qw.QW_EINVAL
+
+
 def test_spectral_bound_matches_oracle(env, oracle_mod):
     torch, qw = env
     n = 20
