@@ -1033,6 +1033,8 @@ qw_status qw_time_pass_c64(int n, int mode, int tb, int nt, int on_the_fly, int 
     a.L = L;
     a.g0 = g0;
     a.h = h;
+    a.pr = 1.f;   // START and ADD outputs are multiplied by pr + i pi
+    a.pi = 0.f;
     a.xcd_order = xcd_order ? 1 : 0;
     launch_pass<float>(a, mode, otf, ntiles, s, TileCfg{tb, nt, true, 0, false});
     QW_HIP(hipGetLastError());
