@@ -213,11 +213,12 @@ qw_status qw_spectral_bound_f64(int n, const double *diag, const double *h, cons
  *             generate them from h, J (host arrays as in qw_spectral_bound_*).
  *             With diag == NULL and n >= 31 the complex64 call recomputes the
  *             diagonal inside every Clenshaw term from per-tile tables and never
- *             stores it (from 26 to 28 qubits the fused passes of the two high
- *             bit groups rebuild it and no pass reads a stored one, although
- *             the workspace still has room for it); complex128 stores it in the
- *             workspace (n = 32: the workspace is 172 GB, with psi 240 GB in
- *             all).  A recomputed value is summed in double and rounded once.
+ *             stores it.  From 26 to 28 qubits the fused passes of the two end
+ *             orientations rebuild it and no pass reads a stored one (complex64
+ *             and complex128; the workspace still has room for it).  Otherwise
+ *             complex128 stores it in the workspace (n = 32: the workspace is
+ *             172 GB, with psi 240 GB in all).  A recomputed value is summed in
+ *             double and rounded once.
  *   psi_in  : device, N complex values; psi_out: device, N complex values; they
  *             may be the same buffer.
  *   tol     : truncation tolerance (absolute, for a unit-norm psi).

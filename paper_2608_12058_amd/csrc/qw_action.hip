@@ -102,7 +102,7 @@ static WsLayout ws_layout(int n, int prec, bool otf)
     L.qt = take(4 * (size_t(1) << TB_WIDE) * sizeof(double));   // split pair tables, per orientation
     // on the fly (every orientation, or the top one of the split shape): per-tile
     // fields, tiles of >= 2^12 amplitudes
-    const bool top = (prec == 64 && n >= OTF_TOP_NMIN && n <= SPLIT_NMAX);
+    const bool top = (n >= OTF_TOP_NMIN && n <= SPLIT_NMAX);
     L.ft = (otf || top) ? take(4 * (N >> TB_NARROW) * TILE_FIELDS * sizeof(double)) : size_t(-1);
     L.coef = (n <= Cfg<float>::TB) ? take((size_t)(KMAX_ONCHIP + 1) * cs) : size_t(-1);
     L.items = take(256);
@@ -272,8 +272,8 @@ static void launch_pass(const PassArgs<R> &a, int mode, bool otf, uint64_t ntile
         return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, true, false>(a, mode, otf, ntiles, s);
     } else {
         if (cfg.nt == NT_NARROW) return launch_shape<R, TB_NARROW, NT_NARROW, false, false>(a, mode, otf, ntiles, s);
-        if (cfg.stream) return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, false, true>(a, mode, otf, ntiles, s, cfg.keep_pd);
-        return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, false, false>(a, mode, otf, ntiles, s);
+        if (cfg.stream) return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, true, true>(a, mode, otf, ntiles, s, cfg.keep_pd);
+        return launch_shape<R, Cfg<R>::TB, Cfg<R>::NT, true, false>(a, mode, otf, ntiles, s);
     }
 }
 
@@ -606,14 +606,14 @@ static qw_status action_impl(int n, const R *diag, const double *h, const double
         const PassPlan &pl = plan[o].pl;
         const TileCfg &pc = plan[o].fused;
         const int log_nt = (pc.nt == 1024) ? 10 : 9;
-        const bool shape_ok = sizeof(R) == 4 && ((pc.tb == TB_WIDE && pc.nt == NT_WIDE) ||
-                                                 (pc.tb == Cfg<R>::TB && pc.nt == Cfg<R>::NT));
+        const bool shape_ok = (sizeof(R) == 4 && pc.tb == TB_WIDE && pc.nt == NT_WIDE) ||
+                              (pc.tb == Cfg<R>::TB && pc.nt == Cfg<R>::NT);
         if (pl.L + pl.h != pc.tb || !shape_ok || pc.tb - log_nt > QS_MAX_R) {
             set_error("internal: on-the-fly tile shape");
             return QW_EINVAL;
         }
         hipLaunchKernelGGL(k_qsplit_orient<0>, dim3(((1 << log_nt) + 255) / 256), dim3(256), 0, s, T.h, n, pl.L,
-                           pl.g0, pl.h, log_nt, norm_inv_r, qt + (size_t)o * (1 << TB_WIDE));
+                           pl.g0, pl.h, log_nt, sizeof(R) == 4 ? 1 : 0, norm_inv_r, qt + (size_t)o * (1 << TB_WIDE));
         const uint64_t nt = N >> (pl.L + pl.h);
         hipLaunchKernelGGL(k_tile_fields<0>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, T.h, n, pl.L,
                            pl.g0, pl.h, nt, norm_c, norm_inv_r, ft + (size_t)o * ft_stride);
@@ -881,7 +881,7 @@ qw_status qw_expm_action_c64_noalloc(int n, const float *diag, const double *h, 
 
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.12 (gfx950, fused passes, per-orientation launch plans, contiguous middle orientation, diagonal rebuilt in the end orientations, flips of a thread's own vectors from registers)"; }
+const char *qw_version(void) { return "qwexp 0.13 (gfx950, fused passes, per-orientation launch plans, contiguous middle orientation, diagonal rebuilt in the end orientations in complex64 and complex128, complex64 flips of a thread's own vectors from registers)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {

@@ -342,8 +342,9 @@ __global__ void __launch_bounds__(256) k_tile_fields(const double *hJ, int n, in
 }
 
 // Pair term of one orientation, split for a block of 2^LOG_NT threads.  Tile
-// element bits: T = bits 1..LOG_NT (the thread's), R = bit 0 and the bits above
-// T (the element's position among the thread's own).  With J'(a, b) the coupling
+// element bits: T = bits t0..t0+LOG_NT-1 (the thread's), R = the others (the
+// element's position among the thread's own): t0 = 1 in complex64 (bit 0 and
+// the bits above T), t0 = 0 in complex128 (the bits above T).  With J'(a, b) the coupling
 // of the index bits of tile bits a, b divided by r,
 //   Q(e) = sum_{a<b} J'(a, b) s_a s_b = QTT(t) + sum_{j in R} s_j G_j(t) + QRR(r),
 //   G_j(t) = sum_{i in T} J'(i, j) s_i(t).
@@ -353,7 +354,7 @@ static constexpr int QS_TT = 0, QS_X = 1024, QS_RR = 1152, QS_MAX_R = 8;
 
 template <int D = 0>
 __global__ void __launch_bounds__(256) k_qsplit_orient(const double *hJ, int n, int L, int g0, int h, int log_nt,
-                                                       double inv_r, double *Qs)
+                                                       int t0, double inv_r, double *Qs)
 {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     const double *J = hJ + n;
@@ -363,15 +364,15 @@ __global__ void __launch_bounds__(256) k_qsplit_orient(const double *hJ, int n, 
         const int x = vb(a), y = vb(b);
         return J[pair_off(n, x < y ? x : y, x < y ? y : x)] * inv_r;
     };
-    auto rbit = [&](int j) { return (j == 0) ? 0 : log_nt + j; };
+    auto rbit = [&](int j) { return (t0 == 1) ? ((j == 0) ? 0 : log_nt + j) : (log_nt + j); };
     if (u < (1 << log_nt)) {
         double q = 0.0;
         for (int a = 0; a < log_nt; ++a)
             for (int b = a + 1; b < log_nt; ++b)
-                q += ((((u >> a) ^ (u >> b)) & 1) ? -1.0 : 1.0) * Jp(1 + a, 1 + b);
+                q += ((((u >> a) ^ (u >> b)) & 1) ? -1.0 : 1.0) * Jp(t0 + a, t0 + b);
         Qs[QS_TT + u] = q;
     }
-    if (u < nr * log_nt) Qs[QS_X + u] = Jp(1 + u % log_nt, rbit(u / log_nt));
+    if (u < nr * log_nt) Qs[QS_X + u] = Jp(t0 + u % log_nt, rbit(u / log_nt));
     if (u < (1 << nr)) {
         double q = 0.0;
         for (int a = 0; a < nr; ++a)
@@ -472,7 +473,11 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     static_assert((1 << LOG_NV) == NT * VE, "power-of-two vectors per slice");
     constexpr int QB = (PER >= 16) ? 4 : (PER >= 8) ? 3 : (PER >= 4) ? 2 : (PER >= 2) ? 1 : 0;
     static_assert((1 << QB) == PER, "power-of-two vectors per thread");
-    const int j_lds = max(0, min(a.h, LOG_NV - a.L));   // group bits below the q bits
+    // group bits read from LDS: in complex64 those below the q bits; complex128
+    // (one element per 16-byte vector) reads every flip from LDS, since keeping
+    // the partners in registers spilled its passes
+    constexpr bool QREG = (VE == 2);
+    const int j_lds = QREG ? max(0, min(a.h, LOG_NV - a.L)) : a.h;
     auto flips = [&](int q, uint32_t e, const V (&arr)[PER], R (&sr)[VE], R (&si)[VE]) {
 #pragma unroll
         for (int v = 0; v < VE; ++v) {
@@ -505,7 +510,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
             for (int j = 0; j < j_lds; ++j) step(j);
         }
 #pragma unroll
-        for (int b = 0; b < QB; ++b) {
+        for (int b = 0; b < (QREG ? QB : 0); ++b) {
             if (LOG_NV + b >= a.L && LOG_NV + b < a.L + a.h) {
                 const V &nb = arr[q ^ (1 << b)];
 #pragma unroll
@@ -520,7 +525,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     // (after the barrier, to keep it out of the registers held across it) or
     // rebuilt from the tile fields (also in FUSED).  Rebuilt: element bits ee =
     // (q NT + thread) VE + v split into the thread's bits T and the rest R
-    // (v and the bits of q, r = v | q << 1, constants of the unrolled loops).
+    // (v and the bits of q: r = v | q << 1 in complex64, r = q in complex128;
+    // constants of the unrolled loops).
     // With the tile fields f and the split pair term (k_qsplit_orient),
     //   E/r = C' + sum_{i in T} s_i f_i + QTT(t) + sum_{j in R} s_j (f_j + G_j(t)) + QRR(r),
     // so each thread forms base = C' + sum_T s_i f_i + QTT(t) and H_j = f_j + G_j(t)
@@ -531,15 +537,18 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     constexpr int NR = OTF ? TB - LOG_NT : 1;   // the tile has TB bits (checked on the host)
     static_assert(NR <= QS_MAX_R, "split pair table");
     double base_t = 0.0, Hj[NR];
+    // thread bit i is tile bit T0 + i (T0 = 1 in complex64, where bit 0 numbers
+    // the pair a thread holds); R bit j is tile bit rbit(j)
+    constexpr int T0 = (VE == 2) ? 1 : 0;
+    auto rbit = [&](int j) { return (VE == 2) ? ((j == 0) ? 0 : LOG_NT + j) : (LOG_NT + j); };
     if constexpr (OTF) {
-        static_assert(VE == 2, "the on-the-fly diagonal is complex64 only");
         const uint32_t t = threadIdx.x;
         base_t = fbase + a.Qt[QS_TT + t];
 #pragma unroll
-        for (int i = 0; i < LOG_NT; ++i) base_t += ((t >> i) & 1) ? -fld[1 + i] : fld[1 + i];
+        for (int i = 0; i < LOG_NT; ++i) base_t += ((t >> i) & 1) ? -fld[T0 + i] : fld[T0 + i];
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
-            double g = fld[(j == 0) ? 0 : LOG_NT + j];
+            double g = fld[rbit(j)];
 #pragma unroll
             for (int i = 0; i < LOG_NT; ++i) {
                 const double x = a.Qt[QS_X + j * LOG_NT + i];
@@ -550,7 +559,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R> &a, uint64_t tile, t
     }
     auto diag_of = [&](uint64_t idx, int q, int v) -> R {
         if constexpr (OTF) {
-            const int r = v | (q << 1);
+            const int r = (VE == 2) ? (v | (q << 1)) : q;
             double s = base_t;
 #pragma unroll
             for (int j = 0; j < NR; ++j) s += ((r >> j) & 1) ? -Hj[j] : Hj[j];
@@ -830,14 +839,16 @@ static constexpr int TB_WIDE = 14, NT_WIDE = 1024;
 static constexpr int TB_NARROW = 12, NT_NARROW = 1024;
 static constexpr int NT_MID = 1024;   // complex64 2^13 tiles, 8 amplitudes per thread
 static constexpr int SPLIT_NMIN = 25, SPLIT_NMAX = 28;
-// Complex64 calls without a caller diagonal rebuild it inside every term from
-// n = OTF_NMIN qubits on, where storing it would crowd the 288 GB; with the
-// split shape from OTF_TOP_NMIN qubits the fused pass of the top orientation
-// rebuilds it too (4 bytes per amplitude less there), the other passes read the
-// stored one.  Rebuilding costs per-thread set-up and double-precision sums,
-// which pay only on that pass (28 qubits, per term: contiguous fused pass 999 us
-// stored, 1095 rebuilt; top fused pass 1114 stored, 1023 rebuilt; 25 qubits,
-// where psi and the diagonal stay in the memory-side cache: 135 against 130).
+// Calls without a caller diagonal rebuild it inside the passes: complex64 in
+// every pass from n = OTF_NMIN qubits on, where storing it would crowd the
+// 288 GB; from OTF_TOP_NMIN to 28 qubits the fused passes of both end
+// orientations, in complex64 (whose middle add pass reads no diagonal, so none
+// is stored) and in complex128.  Rebuilding costs per-thread set-up and
+// double-precision sums: on the strided fused passes of complex64 it pays (28
+// qubits, per term: 1114 us with the stored diagonal, 1023 rebuilt), on a
+// contiguous complex64 fused pass it did not (999 against 1095); complex128
+// saves 8 of its 88 bytes per amplitude on either end.  At 25 qubits psi and
+// the diagonal stay in the memory-side cache and the stored one is as fast.
 static constexpr int OTF_NMIN = 31, OTF_TOP_NMIN = 26;
 
 struct TileCfg {
@@ -965,6 +976,14 @@ template <typename R> inline std::vector<OrientSpec> action_plan(int n, bool dia
     for (const PassPlan &pl : plan)
         S.push_back({pl, pass_cfg<R>(cfg, pl, PM_FUSED), pass_cfg<R>(cfg, pl, PM_ADD), otf_all,
                      (xcd_shape && pl.g0 + pl.h < n) ? 1 : 0});
+    if (sizeof(R) == 8 && diag_from_tables && n >= OTF_TOP_NMIN && n <= SPLIT_NMAX && S.size() >= 2) {
+        // complex128 from 26 to 28 qubits: both end orientations (the contiguous
+        // one and the top bits) rebuild the diagonal in their fused passes, 80
+        // instead of 88 bytes per amplitude, and none is stored (28 qubits: 6.62
+        // -> 6.20 ms per term; the top one alone 6.41; 27: 3.56 -> 3.19)
+        S.front().otf = true;
+        S.back().otf = true;
+    }
     return S;
 }
 
