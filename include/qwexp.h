@@ -211,14 +211,14 @@ qw_status qw_spectral_bound_f64(int n, const double *diag, const double *h, cons
  *   n       : 1..32.
  *   diag    : device, N energies (float for _c64, double for _c128), or NULL to
  *             generate them from h, J (host arrays as in qw_spectral_bound_*).
- *             With diag == NULL and n >= 31 the complex64 call recomputes the
- *             diagonal inside every Clenshaw term from per-tile tables and never
- *             stores it.  From 26 to 28 qubits the fused passes of the two end
- *             orientations rebuild it and no pass reads a stored one (complex64
- *             and complex128; the workspace still has room for it).  Otherwise
- *             complex128 stores it in the workspace (n = 32: the workspace is
- *             172 GB, with psi 240 GB in all).  A recomputed value is summed in
- *             double and rounded once.
+ *             With diag == NULL the fused passes of the two end orientations
+ *             rebuild the diagonal inside every Clenshaw term from per-tile
+ *             tables and no pass reads a stored one: complex64 from 26 qubits
+ *             (n >= 31: it is never stored, and the on-the-fly workspace has no
+ *             room for it; 26-30: the workspace still has), complex128 from 26
+ *             to 28 qubits.  Otherwise complex128 stores it in the workspace
+ *             (n = 32: the workspace is 172 GB, with psi 240 GB in all).  A
+ *             recomputed value is summed in double and rounded once.
  *   psi_in  : device, N complex values; psi_out: device, N complex values; they
  *             may be the same buffer.
  *   tol     : truncation tolerance (absolute, for a unit-norm psi).

@@ -102,7 +102,7 @@ static WsLayout ws_layout(int n, int prec, bool otf)
     L.qt = take(4 * (size_t(1) << TB_WIDE) * sizeof(double));   // split pair tables, per orientation
     // on the fly (every orientation, or the top one of the split shape): per-tile
     // fields, tiles of >= 2^12 amplitudes
-    const bool top = (n >= OTF_TOP_NMIN && n <= SPLIT_NMAX);
+    const bool top = (n >= OTF_TOP_NMIN);
     L.ft = (otf || top) ? take(4 * (N >> TB_NARROW) * TILE_FIELDS * sizeof(double)) : size_t(-1);
     L.coef = (n <= Cfg<float>::TB) ? take((size_t)(KMAX_ONCHIP + 1) * cs) : size_t(-1);
     L.items = take(256);
@@ -881,7 +881,7 @@ qw_status qw_expm_action_c64_noalloc(int n, const float *diag, const double *h, 
 
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.13 (gfx950, fused passes, per-orientation launch plans, contiguous middle orientation, diagonal rebuilt in the end orientations in complex64 and complex128, complex64 flips of a thread's own vectors from registers)"; }
+const char *qw_version(void) { return "qwexp 0.14 (gfx950, fused passes, per-orientation launch plans from 25 qubits, contiguous middle orientation, diagonal rebuilt in the end orientations in complex64 and complex128, complex64 flips of a thread's own vectors from registers)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {

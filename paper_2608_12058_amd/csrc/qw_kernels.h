@@ -928,13 +928,15 @@ struct OrientSpec {
     int xcd;         // blocks take tiles in XCD-major order (xcd_tile)
 };
 
-// Complex64 at 25-28 and 32 qubits: the contiguous orientation in the middle
-// (an add pass every term, 12 or 13 bits), the two high groups at the ends
-// (one fused pass each every other term).  The fused pass of the lower high
-// group runs on 2^14-amplitude tiles with rows of >= 512 B, the top group's on
-// 2^13 (25-28 qubits) or 2^14 (32 qubits) tiles.  Both ends rebuild the
-// diagonal when it comes from (h, J) (from 26 qubits; every pass from 31), so
-// no pass reads a stored one.  Measured per pass at 28 qubits (same box,
+// Complex64 from 25 qubits: the contiguous orientation in the middle (an add
+// pass every term, 12 or 13 bits), the two high groups at the ends (one fused
+// pass each every other term).  The fused pass of the lower high group runs on
+// 2^14-amplitude tiles with rows of >= 512 B (25-28 qubits) or 128 B (30-32
+// qubits; 29: 2^13 tiles, 128 B), the top group's on 2^13 tiles (2^14 at 32
+// qubits).  Both ends rebuild the diagonal when it comes from (h, J) (from 26
+// qubits), so no pass reads a stored one.  At 29-31 qubits this layout took
+// 6078, 12297 and 25867 us per term against 6695, 13348 and 27364 for the
+// contiguous bits in a fused pass at one end with a stored diagonal.  Measured per pass at 28 qubits (same box,
 // microseconds): contiguous add on 2^12 tiles 1005 against 1068 for the old
 // middle group (bits 12-19, 2^13 tiles); fused pass of bits 12-19 on 2^14
 // tiles, 512-byte rows, 1765 against 1981 for the old contiguous fused pass;
@@ -958,6 +960,21 @@ template <typename R> inline std::vector<OrientSpec> action_plan(int n, bool dia
             S.push_back({{0, 0, TB_NARROW}, narrow, narrow, false, 1});
             S.push_back({{Cfg<R>::TB - h2, TB_NARROW + h1, h2}, {Cfg<R>::TB, Cfg<R>::NT, st, 0, kp},
                          {Cfg<R>::TB, NT_MID, st, 0, kp}, otf, 0});
+            return S;
+        }
+        if (n >= 29 && n <= 31) {
+            // the same layout with the fastest shapes of a sweep of pass shapes:
+            // 29 qubits 12 + (9, 8), 30 qubits 12 + (10, 8), 31 qubits 13 + (10, 8) bits
+            const TileCfg wide{TB_WIDE, NT_WIDE, st, 0, false};
+            const TileCfg dflt{Cfg<R>::TB, Cfg<R>::NT, st, 0, false};
+            const TileCfg narrow{TB_NARROW, NT_NARROW, st, 0, false};
+            const bool otf = diag_from_tables;
+            const int c = (n == 31) ? Cfg<R>::TB : TB_NARROW;   // contiguous bits
+            const int h1 = (n == 29) ? 9 : 10, h2 = n - c - h1;
+            const TileCfg end0 = (h1 == 10) ? wide : dflt;       // rows of 128 B either way
+            S.push_back({{end0.tb - h1, c, h1}, end0, end0, otf, 1});
+            S.push_back({{0, 0, c}, (c == TB_NARROW) ? narrow : dflt, (c == TB_NARROW) ? narrow : dflt, false, 1});
+            S.push_back({{Cfg<R>::TB - h2, c + h1, h2}, dflt, dflt, otf, (n == 29) ? 1 : 0});
             return S;
         }
         if (n == 32) {

@@ -77,8 +77,8 @@ N32 = 32
 @pytest.mark.parametrize("n", [31, 32])
 def test_n32_gamma0_on_the_fly_diagonal(env, oracle_mod, n):
     """gamma = 0 at 31 and 32 qubits: exp(-i t E(z)) on |+>, the diagonal
-    recomputed per tile and term (31: 2^13-amplitude tiles with 512 threads,
-    13 + 9 + 9 bits; 32: 2^14 tiles with 1024 threads, 14 + 9 + 9); 512 sampled
+    recomputed per tile in both end passes (31: 10 + 13 + 8 bits, the ends on
+    2^14 and 2^13-amplitude tiles; 32: 10 + 13 + 9, 2^14 tiles); 512 sampled
     amplitudes against E(z) summed by its definition for each sampled z."""
     torch, qw = env
     h, J = synth.sk_instance(n, 0)
@@ -97,7 +97,7 @@ def test_n32_gamma0_on_the_fly_diagonal(env, oracle_mod, n):
 
 def test_n31_c64_on_the_fly_matches_c128_stored(env):
     """31 qubits, gamma = 1, t = 0.3 from |+>: complex64 with the diagonal
-    rebuilt per tile (default 2^13 tiles, 512 threads) against complex128 with
+    rebuilt per tile in both end passes (10 + 13 + 8 bits) against complex128 with
     its stored diagonal, on 4096 sampled amplitudes."""
     torch, qw = env
     n = 31
@@ -115,7 +115,7 @@ def test_n31_c64_on_the_fly_matches_c128_stored(env):
     got128 = y[tidx].cpu().numpy()
     del y, x
     torch.cuda.empty_cache()
-    assert i64["passes"] == 3
+    assert i64["passes"] == 3 and i64["otf_mask"] == 0b101
     assert rel(got64, got128) <= 1e-5
 
 
