@@ -29,7 +29,8 @@ quantum annealing":
                              (Alg. 1), with ``clenshaw`` the evaluation of a
                              caller's Chebyshev series; ``sincos_*_coeffs`` give
                              the sin + cos test function of Figs. 1 and 3 in both
-                             bases.
+                             bases; ``poly_amps_local`` either basis at sampled
+                             outputs, for sizes where no vector fits the host.
   O4 ``anneal_energy_grad``  energy of a piecewise-constant anneal and its
                              gradient by the adjoint of the Clenshaw recurrence
                              (not in the paper; derived from Eq. recursion).
@@ -274,6 +275,76 @@ def horner(n: int, a: np.ndarray, d: np.ndarray, g: float, v: np.ndarray) -> np.
     for k in range(K - 1, -1, -1):
         y = hmatvec(n, d, g, y) + a[k] * v
     return y
+
+
+def _ball_masks(n: int, R: int):
+    """Every n-bit mask of at most R set bits, ordered by bit count (so the masks
+    of at most r bits are a prefix, of length sizes[r]), and the table
+    nb[i, j] = position of masks[i] ^ 2^j (-1 if that has more than R bits)."""
+    import itertools
+    masks, sizes = [], []
+    for r in range(R + 1):
+        for bits in itertools.combinations(range(n), r):
+            masks.append(sum(1 << j for j in bits))
+        sizes.append(len(masks))
+    masks = np.array(masks, dtype=np.int64)
+    order = np.argsort(masks)
+    sm = masks[order]
+    nb = np.full((len(masks), n), -1, dtype=np.int64)
+    for j in range(n):
+        m = masks ^ (1 << j)
+        pos = np.minimum(np.searchsorted(sm, m), len(sm) - 1)
+        hit = sm[pos] == m
+        nb[hit, j] = order[pos[hit]]
+    return masks, sizes, nb
+
+
+def poly_amps_local(n: int, h: np.ndarray, J: np.ndarray, gamma: float, shift: float,
+                    radius: float, coef: np.ndarray, basis: str, factors: np.ndarray,
+                    idx: np.ndarray) -> np.ndarray:
+    """[p(H~) psi](z) at sampled basis indices z, for H~ = (H - shift) / radius,
+    H = diag(E) + gamma sum_j X_j and the product state psi(x) = prod_j
+    factors[j, bit_j(x)] (O5 at sizes where no full vector fits the host).
+
+    p = sum_k coef_k T_k (basis "cheb") or sum_k coef_k x^k ("mono").  A degree-K
+    polynomial in H~ reaches only the indices within Hamming distance K of z, so
+    u_k = T_k(H~) psi (three-term recurrence T_{k+1} = 2 x T_k - T_{k-1},
+    sec. II.B) or H~^k psi is formed on the ball of radius K - k around z, where
+    every flip partner it needs is defined: (H~ u)(x) = ((E(x) - shift) u(x) +
+    gamma sum_j u(x ^ 2^j)) / radius.  E(x) is the SK energy summed by its
+    definition (one matrix product over the ball's spins)."""
+    coef = np.asarray(coef, dtype=np.complex128)
+    K = len(coef) - 1
+    masks, sizes, nb = _ball_masks(n, K)
+    h = np.asarray(h, dtype=np.float64)
+    Jm = np.zeros((n, n))
+    Jm[np.triu_indices(n, 1)] = np.asarray(J, dtype=np.float64)
+    out = np.empty(len(idx), dtype=np.complex128)
+    for q, z in enumerate(np.asarray(idx, dtype=np.int64)):
+        x = int(z) ^ masks
+        bits = (x[:, None] >> np.arange(n)[None, :]) & 1
+        amp = np.prod(np.asarray(factors)[np.arange(n)[None, :], bits], axis=1)
+        s = 1.0 - 2.0 * bits
+        E = s @ h + np.einsum("pj,jk,pk->p", s, Jm, s)
+        dt = (E - shift) / radius
+        g = gamma / radius
+
+        def hop(u, m):
+            # (H~ u) on the first m ball points; u is defined on a larger prefix
+            return dt[:m] * u[:m] + g * u[nb[:m]].sum(axis=1)
+
+        prev, cur = None, amp
+        acc = coef[0] * cur[0]
+        for k in range(1, K + 1):
+            m = sizes[K - k]
+            if basis == "cheb":
+                nxt = hop(cur, m) if k == 1 else 2.0 * hop(cur, m) - prev[:m]
+            else:
+                nxt = hop(cur, m)
+            prev, cur = cur, nxt
+            acc += coef[k] * cur[0]
+        out[q] = acc
+    return out
 
 
 def sincos_taylor_coeffs(s: float, K: int) -> np.ndarray:

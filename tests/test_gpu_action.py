@@ -393,7 +393,7 @@ def test_n28_bench_workload_vs_oracle_golden(env, prec):
 # ---------------------------------------- complex64 at 29 and 30 qubits
 
 @pytest.mark.parametrize("n,gamma,t,seed", [(29, 0.9, 0.4, 629), (30, -0.8, -0.3, 630)])
-def test_default_shape_n29_n30_c64_matches_c128(env, n, gamma, t, seed):
+def test_n29_n30_c64_matches_c128(env, n, gamma, t, seed):
     """29 and 30 qubits, where the oracle is too slow for a test: complex64 with
     the contiguous 12 bits in the middle orientation and the diagonal rebuilt in
     both end passes (9 + 12 + 8 and 10 + 12 + 8 bits) against complex128 with its

@@ -584,6 +584,65 @@ def test_sincos_chebyshev_coefficients(oracle_mod, s):
     assert np.max(np.abs(p - (np.sin(s * x) + np.cos(s * x)))) < 1e-13
 
 
+@pytest.mark.parametrize("basis", ["cheb", "mono"])
+def test_poly_amps_local_vs_dense_eigendecomposition(oracle_mod, basis):
+    """The sampled-output evaluation against the spectral definition p(H~) psi =
+    V p(Lambda) V^H psi, with H~ the dense Kronecker-built Hamiltonian (numpy
+    eigh) and p evaluated at the eigenvalues by numpy's chebval / polyval; every
+    output of a 9-qubit instance, degree 5, gamma != 0, a shift and a radius that
+    is not the spectral bound."""
+    n = 9
+    h, J = synth.sk_instance(n, 31)
+    fac = synth.product_state_factors(n, 32)
+    psi = synth.product_state(fac)
+    E = oracle_mod.energies(n, h, J)
+    gamma, c, r = 0.7, 0.3, 9.5
+    rng = np.random.default_rng(33)
+    coef = rng.standard_normal(6) + 1j * rng.standard_normal(6)
+    Ht = (oracle_mod.hamiltonian_dense(n, E, gamma) - c * np.eye(1 << n)) / r
+    w, V = np.linalg.eigh(Ht)
+    ev = np.polynomial.chebyshev.chebval if basis == "cheb" else np.polynomial.polynomial.polyval
+    ref = V @ (ev(w, coef) * (V.conj().T @ psi))
+    got = oracle_mod.poly_amps_local(n, h, J, gamma, c, r, coef, basis, fac, np.arange(1 << n))
+    assert rel(got, ref) < 1e-13
+
+
+def test_poly_amps_local_gamma_zero_is_chebval(oracle_mod):
+    """gamma = 0 at 30 qubits: p(H~) psi at z is chebval(d~(z)) psi(z) with
+    d~(z) = (E(z) - c) / r and E(z) summed by its definition per sampled index."""
+    n = 30
+    h, J = synth.sk_instance(n, 34)
+    fac = synth.product_state_factors(n, 35)
+    idx = np.random.default_rng(36).integers(0, 1 << n, 6)
+    coef = np.array([0.5, -0.25 + 0.1j, 0.3, 0.2j])
+    c, r = -0.4, 60.0
+    amp = np.ones(len(idx), dtype=np.complex128)
+    for j in range(n):
+        amp *= fac[j, (idx >> j) & 1]
+    ref = np.polynomial.chebyshev.chebval((oracle_mod.energies_at(n, h, J, idx) - c) / r, coef) * amp
+    got = oracle_mod.poly_amps_local(n, h, J, 0.0, c, r, coef, "cheb", fac, idx)
+    assert rel(got, ref) < 1e-14
+
+
+@pytest.mark.parametrize("basis", ["cheb", "mono"])
+def test_poly_amps_local_matches_full_vector_recurrences(oracle_mod, basis):
+    """At 14 qubits: sampled outputs against the full-vector clenshaw / horner
+    (Alg. 2 / Alg. 1) on the same normalised diagonal, degree 6."""
+    n = 14
+    h, J = synth.sk_instance(n, 37)
+    fac = synth.product_state_factors(n, 38)
+    psi = synth.product_state(fac)
+    E = oracle_mod.energies(n, h, J)
+    gamma, c, r = -0.6, 0.2, 25.0
+    rng = np.random.default_rng(39)
+    coef = rng.standard_normal(7) + 1j * rng.standard_normal(7)
+    d, g = (E - c) / r, gamma / r
+    full = oracle_mod.clenshaw(n, coef, d, g, psi) if basis == "cheb" else oracle_mod.horner(n, coef, d, g, psi)
+    idx = np.concatenate([[0, (1 << n) - 1], rng.integers(0, 1 << n, 30)])
+    got = oracle_mod.poly_amps_local(n, h, J, gamma, c, r, coef, basis, fac, idx)
+    assert rel(got, full[idx]) < 1e-13
+
+
 def test_pins_catch_a_shifted_horner_coefficient(oracle_mod, monkeypatch):
     """Plant y <- H y + a_{k+1} v (an off-by-one in Alg. 1): the dense pin fails."""
     def broken(n, a, d, g, v):
