@@ -833,17 +833,17 @@ template <typename R> inline std::vector<PassPlan> plan_passes(int n)
 // with the same pass count: at 28 qubits 12 + 8 + 8 bits instead of 13 + 8 + 7,
 // 3306 -> 3186 us per term (the contiguous fused pass 1095 -> 998 us, the add
 // pass 1114 -> 1077); 25, 26, 27 qubits: 405 -> 396, 818 -> 792, 1650 -> 1604 us.
-// From 29 qubits the high bits would need a group of 9 (128-byte rows) or one
-// more pass.
+// From 29 qubits one high group takes 9 or 10 bits (128-byte rows): the
+// per-orientation plans of action_plan.
 static constexpr int TB_WIDE = 14, NT_WIDE = 1024;
 static constexpr int TB_NARROW = 12, NT_NARROW = 1024;
 static constexpr int NT_MID = 1024;   // complex64 2^13 tiles, 8 amplitudes per thread
 static constexpr int SPLIT_NMIN = 25, SPLIT_NMAX = 28;
-// Calls without a caller diagonal rebuild it inside the passes: complex64 in
-// every pass from n = OTF_NMIN qubits on, where storing it would crowd the
-// 288 GB; from OTF_TOP_NMIN to 28 qubits the fused passes of both end
-// orientations, in complex64 (whose middle add pass reads no diagonal, so none
-// is stored) and in complex128.  Rebuilding costs per-thread set-up and
+// Calls without a caller diagonal rebuild it inside the passes: from
+// OTF_TOP_NMIN qubits on the fused passes of both end orientations, in
+// complex64 (whose middle add pass reads no diagonal, so none is formed) and,
+// up to 28 qubits, in complex128.  From OTF_NMIN qubits complex64 has no room
+// for a stored diagonal at all (storing it would crowd the 288 GB).  Rebuilding costs per-thread set-up and
 // double-precision sums: on the strided fused passes of complex64 it pays (28
 // qubits, per term: 1114 us with the stored diagonal, 1023 rebuilt), on a
 // contiguous complex64 fused pass it did not (999 against 1095); complex128
