@@ -421,3 +421,47 @@ def test_n29_n30_c64_matches_c128(env, n, gamma, t, seed):
     torch.cuda.empty_cache()
     assert err <= C64_TOL
     assert abs(n64 - 1.0) <= C64_TOL and abs(n128 - 1.0) <= 1e-11
+
+
+def _energies_torch(torch, n, h, J):
+    """E(z) = sum_{j<k} J_jk s_j s_k + sum_j h_j s_j for every z, in float64 on the
+    device from its definition (torch matrix products over chunks of indices),
+    rounded once to float32."""
+    dev = "cuda"
+    hv = torch.as_tensor(h, dtype=torch.float64, device=dev)
+    Jm = torch.zeros((n, n), dtype=torch.float64, device=dev)
+    iu = torch.triu_indices(n, n, 1, device=dev)
+    Jm[iu[0], iu[1]] = torch.as_tensor(J, dtype=torch.float64, device=dev)
+    E = torch.empty(1 << n, dtype=torch.float32, device=dev)
+    ar = torch.arange(n, device=dev)
+    chunk = 1 << 22
+    for lo in range(0, 1 << n, chunk):
+        z = torch.arange(lo, lo + chunk, device=dev, dtype=torch.int64)
+        s = 1.0 - 2.0 * ((z[:, None] >> ar[None, :]) & 1).to(torch.float64)
+        E[lo:lo + chunk] = (s @ hv + ((s @ Jm) * s).sum(dim=1)).to(torch.float32)
+    return E
+
+
+def test_n29_caller_diagonal_c64_matches_tables(env):
+    """29 qubits, complex64 with a caller diagonal (float32 energies formed on the
+    device from their definition): the end passes read the stored normalised
+    diagonal instead of rebuilding it from (h, J).  Against the call from (h, J)
+    over the whole vector on a seeded product state: <= 1e-5."""
+    torch, qw = env
+    n = 29
+    h, J = synth.sk_instance(n, 731)
+    fac = synth.product_state_factors(n, 732)
+    E = _energies_torch(torch, n, h, J)
+    x = synth.product_state_torch(fac, "cuda", torch.complex64)
+    y_tab, i_tab = qw.expm_action(x, 0.7, 0.35, h=h, J=J)
+    y_dia, i_dia = qw.expm_action(x, 0.7, 0.35, diag=E)
+    del x, E
+    assert i_tab["passes"] == 3 and i_dia["passes"] == 3
+    assert i_tab["otf_mask"] == 0b101 and i_dia["otf_mask"] == 0
+    d = y_tab.to(torch.complex128)
+    ref = y_dia.to(torch.complex128)
+    err = (torch.linalg.vector_norm(d - ref) / torch.linalg.vector_norm(ref)).item()
+    print(f"n=29 caller diagonal vs (h, J): K {i_dia['K']} / {i_tab['K']}, {err:.2e}", flush=True)
+    del d, ref, y_tab, y_dia
+    torch.cuda.empty_cache()
+    assert err <= C64_TOL
