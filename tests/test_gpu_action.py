@@ -22,6 +22,7 @@ import numpy as np
 import pytest
 
 import synth
+from device_energies import energies_torch
 
 pytestmark = pytest.mark.gpu
 
@@ -423,25 +424,6 @@ def test_n29_n30_c64_matches_c128(env, n, gamma, t, seed):
     assert abs(n64 - 1.0) <= C64_TOL and abs(n128 - 1.0) <= 1e-11
 
 
-def _energies_torch(torch, n, h, J):
-    """E(z) = sum_{j<k} J_jk s_j s_k + sum_j h_j s_j for every z, in float64 on the
-    device from its definition (torch matrix products over chunks of indices),
-    rounded once to float32."""
-    dev = "cuda"
-    hv = torch.as_tensor(h, dtype=torch.float64, device=dev)
-    Jm = torch.zeros((n, n), dtype=torch.float64, device=dev)
-    iu = torch.triu_indices(n, n, 1, device=dev)
-    Jm[iu[0], iu[1]] = torch.as_tensor(J, dtype=torch.float64, device=dev)
-    E = torch.empty(1 << n, dtype=torch.float32, device=dev)
-    ar = torch.arange(n, device=dev)
-    chunk = 1 << 22
-    for lo in range(0, 1 << n, chunk):
-        z = torch.arange(lo, lo + chunk, device=dev, dtype=torch.int64)
-        s = 1.0 - 2.0 * ((z[:, None] >> ar[None, :]) & 1).to(torch.float64)
-        E[lo:lo + chunk] = (s @ hv + ((s @ Jm) * s).sum(dim=1)).to(torch.float32)
-    return E
-
-
 def test_n29_caller_diagonal_c64_matches_tables(env):
     """29 qubits, complex64 with a caller diagonal (float32 energies formed on the
     device from their definition): the end passes read the stored normalised
@@ -451,7 +433,7 @@ def test_n29_caller_diagonal_c64_matches_tables(env):
     n = 29
     h, J = synth.sk_instance(n, 731)
     fac = synth.product_state_factors(n, 732)
-    E = _energies_torch(torch, n, h, J)
+    E = energies_torch(torch, n, h, J, torch.float32)
     x = synth.product_state_torch(fac, "cuda", torch.complex64)
     y_tab, i_tab = qw.expm_action(x, 0.7, 0.35, h=h, J=J)
     y_dia, i_dia = qw.expm_action(x, 0.7, 0.35, diag=E)

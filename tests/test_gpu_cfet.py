@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import synth
+from device_energies import energies_torch
 from test_oracle_cfet import exact
 
 pytestmark = pytest.mark.gpu
@@ -103,6 +104,35 @@ def test_constant_schedule_single_step(env, oracle_mod):
     E = oracle_mod.energies(n, h, J)
     ref = oracle_mod.expm_action(n, 0.6 * E, 0.9, T, psi, 1e-13)
     assert rel(y, ref) <= tol
+
+
+@pytest.mark.parametrize("n,prec", [(26, 64), (26, 128), (29, 64)])
+def test_constant_schedule_large_n_vs_caller_diagonal(env, n, prec):
+    """A constant schedule at sizes where the action rebuilds the diagonal from
+    (h, J) in its end passes (26 qubits in both precisions, 29 in complex64): each
+    of the anneal's exponentials scales the prepared energy tables by A, and the
+    rebuilt diagonal must follow that scale.  One adaptive step, against one
+    plain action with the caller diagonal a E (energies formed on the device from
+    their definition; its passes read the stored diagonal), whole vector."""
+    torch, qw = env
+    T, a, b = 1.2, 0.6, 0.9
+    h, J = synth.sk_instance(n, 1800 + n)
+    fac = synth.product_state_factors(n, 1900 + n)
+    cdt, rdt = (torch.complex64, torch.float32) if prec == 64 else (torch.complex128, torch.float64)
+    tol = 1e-7 if prec == 64 else 1e-10
+    psi = synth.product_state_torch(fac, "cuda", cdt)
+    y, info, hs = qw.anneal_cfet4(psi, h, J, [a], [b], T, steps=0, tol=tol)
+    assert info["steps"] == 1 and hs[0] == T
+    E = energies_torch(torch, n, a * np.asarray(h), a * np.asarray(J), rdt)
+    ref, iref = qw.expm_action(psi, b, T, diag=E, tol=2.0 ** -23 if prec == 64 else 1e-13)
+    del psi, E
+    assert iref["otf_mask"] == 0
+    d = y.to(torch.complex128) - ref.to(torch.complex128)
+    err = (torch.linalg.vector_norm(d) / torch.linalg.vector_norm(ref.to(torch.complex128))).item()
+    print(f"n={n} c{prec}: anneal (rebuilt diagonal) vs caller diagonal {err:.2e}", flush=True)
+    del d, y, ref
+    torch.cuda.empty_cache()
+    assert err <= (C64_TOL if prec == 64 else tol)
 
 
 def test_c64_matches_c128_at_24_qubits(env):
