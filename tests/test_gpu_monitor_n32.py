@@ -48,6 +48,30 @@ def test_monitor_bound_holds(env, oracle_mod, prec, n):
     assert err <= tol + info["K"] * 2.0 ** -53 + info["eval_bound"] + rep
 
 
+@pytest.mark.parametrize("n", [26, 29])
+def test_monitor_with_rebuilt_diagonal(env, n):
+    """The norm monitor where both end passes rebuild the diagonal (complex64, 26
+    and 29 qubits): the output matches the unmonitored call, the fused norm of
+    the output equals the norm torch measures, ||b_k|| never exceeds its limit
+    and the evaluation bound is positive and finite."""
+    torch, qw = env
+    h, J = synth.sk_instance(n, 95)
+    fac = synth.product_state_factors(n, 96)
+    x = synth.product_state_torch(fac, "cuda", torch.complex64)
+    y0, i0 = qw.expm_action(x, 0.9, 1.0, h=h, J=J)
+    y1, i1 = qw.expm_action(x, 0.9, 1.0, h=h, J=J, monitor=True)
+    del x
+    assert i1["otf_mask"] == 0b101 and i1["K"] == i0["K"]
+    d = (torch.linalg.vector_norm(y1 - y0) / torch.linalg.vector_norm(y0)).item()
+    nrm = torch.linalg.vector_norm(y1.to(torch.complex128)).item()
+    del y0, y1
+    torch.cuda.empty_cache()
+    assert d <= 1e-6
+    assert abs(i1["out_norm"] - nrm) <= 1e-6 * nrm
+    assert i1["growth"] <= 1.0
+    assert 0 < i1["eval_bound"] < np.inf
+
+
 @pytest.mark.parametrize("prec", [64, 128])
 def test_given_bound_matches_and_small_radius_diverges(env, oracle_mod, prec):
     torch, qw = env
