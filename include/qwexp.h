@@ -216,7 +216,7 @@ qw_status qw_spectral_bound_f64(int n, const double *diag, const double *h, cons
  *             tables and no pass reads a stored one: complex64 from 26 qubits
  *             (n >= 31: it is never stored, and the on-the-fly workspace has no
  *             room for it; 26-30: the workspace still has), complex128 from 26
- *             to 28 qubits.  Otherwise complex128 stores it in the workspace
+ *             to 30 qubits.  Otherwise complex128 stores it in the workspace
  *             (n = 32: the workspace is 172 GB, with psi 240 GB in all).  A
  *             recomputed value is summed in double and rounded once.
  *   psi_in  : device, N complex values; psi_out: device, N complex values; they

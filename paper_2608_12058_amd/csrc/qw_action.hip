@@ -8,9 +8,9 @@
 //
 // Device layout: psi, b1, b2 are interleaved complex vectors of N = 2^n
 // amplitudes (bit j of the index = qubit j); the normalised diagonal
-// d = (E - c)/r is a real vector of N (recomputed per tile instead in complex64
-// for n >= 31, where storing it would crowd the 288 GB, and in the top
-// orientation's fused pass from 26 to 28 qubits).
+// d = (E - c)/r is a real vector of N, or recomputed per tile in the fused
+// passes of both end orientations: complex64 from 26 qubits (from 31 never
+// stored, where it would crowd the 288 GB), complex128 from 26 to 30 qubits.
 //
 // Per Clenshaw term the state is streamed in P passes (P = 1 for n <= 13 in
 // complex64): the first pass loads a contiguous tile of 2^13 amplitudes of
@@ -881,7 +881,7 @@ qw_status qw_expm_action_c64_noalloc(int n, const float *diag, const double *h, 
 
 
 const char *qw_last_error(void) { return g_err.c_str(); }
-const char *qw_version(void) { return "qwexp 0.14 (gfx950, fused passes, per-orientation launch plans from 25 qubits, contiguous middle orientation, diagonal rebuilt in the end orientations in complex64 and complex128, complex64 flips of a thread's own vectors from registers)"; }
+const char *qw_version(void) { return "qwexp 0.15 (gfx950, fused passes, per-orientation launch plans from 25 qubits, contiguous middle orientation, diagonal rebuilt in the end orientations in complex64 and complex128, complex64 flips of a thread's own vectors from registers)"; }
 
 size_t qw_workspace_bytes(int n, int precision, int on_the_fly)
 {

@@ -842,14 +842,14 @@ static constexpr int SPLIT_NMIN = 25, SPLIT_NMAX = 28;
 // Calls without a caller diagonal rebuild it inside the passes: from
 // OTF_TOP_NMIN qubits on the fused passes of both end orientations, in
 // complex64 (whose middle add pass reads no diagonal, so none is formed) and,
-// up to 28 qubits, in complex128.  From OTF_NMIN qubits complex64 has no room
+// up to C128_OTF_NMAX qubits, in complex128.  From OTF_NMIN qubits complex64 has no room
 // for a stored diagonal at all (storing it would crowd the 288 GB).  Rebuilding costs per-thread set-up and
 // double-precision sums: on the strided fused passes of complex64 it pays (28
 // qubits, per term: 1114 us with the stored diagonal, 1023 rebuilt), on a
 // contiguous complex64 fused pass it did not (999 against 1095); complex128
 // saves 8 of its 88 bytes per amplitude on either end.  At 25 qubits psi and
 // the diagonal stay in the memory-side cache and the stored one is as fast.
-static constexpr int OTF_NMIN = 31, OTF_TOP_NMIN = 26;
+static constexpr int OTF_NMIN = 31, OTF_TOP_NMIN = 26, C128_OTF_NMAX = 30;
 
 struct TileCfg {
     int tb, nt;
@@ -993,11 +993,13 @@ template <typename R> inline std::vector<OrientSpec> action_plan(int n, bool dia
     for (const PassPlan &pl : plan)
         S.push_back({pl, pass_cfg<R>(cfg, pl, PM_FUSED), pass_cfg<R>(cfg, pl, PM_ADD), otf_all,
                      (xcd_shape && pl.g0 + pl.h < n) ? 1 : 0});
-    if (sizeof(R) == 8 && diag_from_tables && n >= OTF_TOP_NMIN && n <= SPLIT_NMAX && S.size() >= 2) {
-        // complex128 from 26 to 28 qubits: both end orientations (the contiguous
+    if (sizeof(R) == 8 && diag_from_tables && n >= OTF_TOP_NMIN && n <= C128_OTF_NMAX && S.size() >= 2) {
+        // complex128 from 26 to 30 qubits: both end orientations (the contiguous
         // one and the top bits) rebuild the diagonal in their fused passes, 80
-        // instead of 88 bytes per amplitude, and none is stored (28 qubits: 6.62
-        // -> 6.20 ms per term; the top one alone 6.41; 27: 3.56 -> 3.19)
+        // instead of 88 bytes per amplitude, and none is formed (28 qubits: 6.62
+        // -> 6.20 ms per term; the top one alone 6.41; 27: 3.56 -> 3.19; 29:
+        // 14.00 -> 13.80; 30: 31.78 -> 29.17).  At 31 and 32 qubits complex128
+        // keeps its stored diagonal.
         S.front().otf = true;
         S.back().otf = true;
     }

@@ -397,8 +397,10 @@ def test_n28_bench_workload_vs_oracle_golden(env, prec):
 def test_n29_n30_c64_matches_c128(env, n, gamma, t, seed):
     """29 and 30 qubits, where the oracle is too slow for a test: complex64 with
     the contiguous 12 bits in the middle orientation and the diagonal rebuilt in
-    both end passes (9 + 12 + 8 and 10 + 12 + 8 bits) against complex128 with its
-    stored diagonal on 2^12 tiles (12 + 9 + 8 and 12 + 9 + 9 bits), a
+    both end passes (9 + 12 + 8 and 10 + 12 + 8 bits) against complex128 on 2^12
+    tiles (12 + 9 + 8 and 12 + 9 + 9 bits, its end passes rebuilding the diagonal
+    in double; the stored diagonal is checked against the rebuilt one by
+    test_n29_caller_diagonal_c64_matches_tables), a
     generic SK instance and a seeded product state (not an eigenvector), over the
     whole vector on the GPU: <= 1e-5; both norms stay 1 (the 30-qubit case with
     negative gamma and t)."""
