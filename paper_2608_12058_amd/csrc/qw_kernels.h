@@ -936,14 +936,15 @@ struct OrientSpec {
 // qubits).  Both ends rebuild the diagonal when it comes from (h, J) (from 26
 // qubits), so no pass reads a stored one.  At 29-31 qubits this layout took
 // 6078, 12297 and 25867 us per term against 6695, 13348 and 27364 for the
-// contiguous bits in a fused pass at one end with a stored diagonal.  Measured per pass at 28 qubits (same box,
-// microseconds): contiguous add on 2^12 tiles 1005 against 1068 for the old
-// middle group (bits 12-19, 2^13 tiles); fused pass of bits 12-19 on 2^14
-// tiles, 512-byte rows, 1765 against 1981 for the old contiguous fused pass;
-// top group (bits 20-27) 2030 either way: 2902 against 3074 per term.  At 32
-// qubits (13 + 10 + 9 bits): 50.3 against 53.3 ms per term.  XCD-major order
-// helps the contiguous passes (1005 against 1053) and slows the strided fused
-// ones (1765 against 1810).
+// contiguous bits in a fused pass at one end with a stored diagonal.  Measured
+// per pass at 28 qubits (same box, microseconds): contiguous add on 2^12 tiles
+// 1005 against 1068 for the old middle group (bits 12-19, 2^13 tiles); fused
+// pass of bits 12-19 on 2^14 tiles, 512-byte rows, 1765 against 1981 for the
+// old contiguous fused pass; top group (bits 20-27) 2030 either way: 2902
+// against 3074 per term.  At 32 qubits (13 + 10 + 9 bits): 50.3 against 53.3
+// ms per term.  XCD-major order helps the contiguous passes (1005 against
+// 1053) and, at 28 qubits, slows the strided fused ones (1765 against 1810);
+// from 29 qubits the sweep chose it for the lower high group.
 template <typename R> inline std::vector<OrientSpec> action_plan(int n, bool diag_from_tables)
 {
     std::vector<OrientSpec> S;
