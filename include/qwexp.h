@@ -54,8 +54,8 @@ typedef enum {
 
 typedef enum { QW_CHEB = 0, QW_CF = 1 } qw_method;
 
-/* Filled on the host before an action call returns (may be NULL).  The only
- * input field is `timing`; every other field is output. */
+/* Filled on the host before an action call returns (may be NULL).  The input
+ * fields are `timing` and `monitor`; every other field is output. */
 typedef struct {
     int n;              /* qubits                                                 */
     int K;              /* polynomial degree; K+1 coefficients                    */
